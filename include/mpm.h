@@ -1,0 +1,260 @@
+/*
+ * mpm.h - exact multiple pattern matching on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Kouzinopoulos, Assael, Pyrgiotis, Margaritis, "A Hybrid
+ * Parallel Implementation of the Aho-Corasick and Wu-Manber Algorithms Using
+ * NVIDIA CUDA and MPI", Section 1, Definition): given a text T of n bytes and
+ * d patterns of equal length m, report every pair (i, r) such that the m bytes
+ * of T starting at i equal pattern r. Two index kinds solve it:
+ *
+ *   - Aho-Corasick (Section 3.1, Algorithms 1-3): the goto/supply automaton,
+ *     flattened into a dense transition table (Section 3.1, the array
+ *     representation that precomputes every supply transition).
+ *   - Wu-Manber (Section 3.2, Algorithms 4-5): SHIFT/HASH/PREFIX tables over
+ *     B-character blocks with direct verification.
+ *
+ * Results are bit-identical whichever index or launch variant is used: the
+ * list of (position, pattern id) pairs in ascending (position, id) order,
+ * every id of a duplicated pattern included.
+ *
+ * Conventions
+ *   - Host pointers are plain CPU memory; "device" pointers are HIP device
+ *     memory of the current device. Streams are hipStream_t passed as void*
+ *     (NULL = the default stream).
+ *   - Every call returns an mpm_status; nothing is thrown across this
+ *     boundary. On failure mpm_last_error() describes the cause (thread-local
+ *     string, valid until the next call on the same thread).
+ *   - Device memory is supplied by the caller (the index image, the
+ *     workspace, the outputs); the library allocates device memory only for
+ *     batch plans' small descriptor tables when asked to (see mpm_batch_*).
+ *   - Positions are uint32: texts must be shorter than 2^32 bytes.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mpm_status;
+#define MPM_OK 0
+#define MPM_EINVAL (-1)        /* bad argument (null pointer, d == 0, m == 0, bad variant) */
+#define MPM_EOVERFLOW (-2)     /* more matches than the output capacity */
+#define MPM_ENOMEM (-3)        /* host allocation failed or a caller buffer is too small */
+#define MPM_EHIP (-4)          /* a HIP runtime call failed */
+#define MPM_ETOOBIG (-5)       /* text of 2^32 bytes or more, or tables beyond the encodable size */
+#define MPM_EUNSUPPORTED (-6)  /* valid request this index cannot serve (e.g. Wu-Manber with m < B) */
+#define MPM_ESTATE (-7)        /* index not uploaded, or the device reported a failed look-back */
+
+typedef struct mpm_index mpm_index;
+
+/* One occurrence: pattern `id` (0-based, its row in the pattern array) starts
+ * at byte `pos` of the text (Section 1: the i of the Definition; Algorithm 3
+ * reports it as i - m + 1 from the end of the window). */
+typedef struct {
+    uint32_t pos;
+    uint32_t id;
+} mpm_match;
+
+#define MPM_ALGO_AC 1
+#define MPM_ALGO_WM 2
+
+/* Build options. Zero-initialise and set what you need; NULL means defaults. */
+typedef struct {
+    /* Wu-Manber block length B in characters (Section 3.2). 0 lets the
+     * builder choose the B that minimises the expected work per text byte for
+     * uniformly random text over the patterns' alphabet. Must satisfy
+     * 1 <= B <= min(m, 8). Ignored by mpm_build_ac. */
+    uint32_t wm_block;
+    uint32_t reserved[7];
+} mpm_opts;
+
+#define MPM_PLACE_AUTO 0    /* LDS when the tables fit beside the scan's own LDS use, else global */
+#define MPM_PLACE_LDS 1     /* matching tables copied into LDS once per workgroup */
+#define MPM_PLACE_GLOBAL 2  /* matching tables read through the L2/L1 caches */
+
+/* Launch variant of a scan. Zero fields take defaults. The text is split
+ * into chunks of lane_bytes * block_threads starting positions; each lane owns
+ * lane_bytes consecutive starting positions and reads m - 1 bytes past them
+ * (Section 4.2.1: sub-chunks with an m - 1 character overlap). */
+typedef struct {
+    uint32_t lane_bytes;     /* multiple of 16, 16..4096 (default 64 for AC, 64 for WM) */
+    uint32_t block_threads;  /* 256, 512 or 1024 (default 256) */
+    uint32_t placement;      /* MPM_PLACE_* */
+    uint32_t grid;           /* workgroups launched; 0 = enough to fill the device */
+} mpm_variant;
+
+/* Facts about a built index. */
+typedef struct {
+    uint32_t algo;           /* MPM_ALGO_AC or MPM_ALGO_WM */
+    uint32_t m;              /* pattern length */
+    uint32_t d;              /* number of patterns */
+    uint32_t d_unique;       /* distinct pattern strings */
+    uint32_t max_dup;        /* most ids sharing one string */
+    uint32_t n_classes;      /* AC: distinct pattern bytes (symbol classes) */
+    uint64_t n_states;       /* AC: automaton states (trie nodes) */
+    uint32_t state_bytes;    /* AC: 2 (uint16 entries) or 4 (uint32) */
+    uint32_t wm_block;       /* WM: chosen B */
+    uint32_t wm_code_shift;  /* WM: block characters hash as (byte >> shift) & 3 */
+    uint32_t wm_zero_shift;  /* WM: SHIFT entries equal to zero */
+    double wm_mean_shift;    /* WM: mean SHIFT over all block hashes */
+    uint64_t table_bytes;    /* bytes of the matching tables read by the scan loop */
+    uint64_t device_bytes;   /* size of the device image (mpm_device_bytes) */
+} mpm_info;
+
+/* ---------------------------------------------------------------------- */
+/* Building                                                                */
+/* ---------------------------------------------------------------------- */
+
+/* Aho-Corasick index (Section 3.1, Algorithm 1 for the goto function,
+ * Algorithm 2 for the supply function, flattened so that every transition
+ * the supply function would simulate is precomputed).
+ *   patterns: host, d rows of m bytes, row-major; any byte values. Copied.
+ *   out:      receives the index; release with mpm_free.
+ * Errors: EINVAL (null pointer, d == 0, m == 0), ETOOBIG (more than 2^31
+ * automaton states), ENOMEM. Host-only: touches no GPU. */
+mpm_status mpm_build_ac(const uint8_t *patterns, uint32_t d, uint32_t m,
+                        const mpm_opts *opts, mpm_index **out);
+
+/* Wu-Manber index (Section 3.2, Algorithm 4: SHIFT initialised to m - B + 1
+ * and lowered to the distance of each block's rightmost occurrence from the
+ * pattern end; HASH lists the patterns per suffix-block hash in ascending
+ * order; PREFIX holds each pattern's leading bytes). Blocks hash 2 bits per
+ * character. Arguments and errors as mpm_build_ac, plus EUNSUPPORTED when
+ * opts->wm_block is outside 1..min(m, 8). Host-only. */
+mpm_status mpm_build_wm(const uint8_t *patterns, uint32_t d, uint32_t m,
+                        const mpm_opts *opts, mpm_index **out);
+
+/* Release an index (host memory only; the caller owns the device image).
+ * NULL is accepted. */
+void mpm_free(mpm_index *idx);
+
+/* Size in bytes of the index's device image. */
+uint64_t mpm_device_bytes(const mpm_index *idx);
+
+/* Copy the index's tables into caller-owned device memory d_buf (at least
+ * mpm_device_bytes bytes, 256-byte aligned) on `stream`, then wait for the
+ * copy. The index keeps d_buf (not a copy): the caller keeps it alive and
+ * unchanged while the index is used for scans.
+ * Errors: EINVAL, ENOMEM (bytes too small), EHIP. */
+mpm_status mpm_upload(mpm_index *idx, void *d_buf, uint64_t bytes, void *stream);
+
+/* Describe an index. Errors: EINVAL. */
+mpm_status mpm_index_info(const mpm_index *idx, mpm_info *out);
+
+/* ---------------------------------------------------------------------- */
+/* Scanning one text                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Workspace needed by mpm_scan for a text of n bytes under variant v (NULL =
+ * default). Errors: EINVAL. */
+mpm_status mpm_workspace_bytes(const mpm_index *idx, uint64_t n, const mpm_variant *v,
+                               uint64_t *bytes);
+
+/* Find every occurrence of every pattern in d_text (Section 1, Definition).
+ * Enqueued on `stream`; returns without waiting.
+ *   d_text:   device, n bytes, any alignment. n < m is legal (no matches).
+ *   d_out:    device, room for `capacity` pairs; may be NULL iff capacity == 0.
+ *             Receives the first min(total, capacity) pairs of the sorted list.
+ *   d_work:   device workspace of at least mpm_workspace_bytes bytes, 8-byte
+ *             aligned, zero-filled before its first use; the scan leaves it
+ *             ready for the next scan. Scans that overlap in time must not
+ *             share a workspace.
+ *   d_total:  device uint64; receives the full number of pairs (may exceed
+ *             capacity; the caller compares).
+ *   v:        launch variant; NULL = defaults.
+ * Errors: EINVAL, ETOOBIG (n >= 2^32), ESTATE (index not uploaded), ENOMEM
+ * (workspace too small), EHIP (launch failed). Device-side errors (a
+ * look-back that never completes) set a flag read by mpm_scan_sync. */
+mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n,
+                    mpm_match *d_out, uint64_t capacity, void *d_work, uint64_t work_bytes,
+                    uint64_t *d_total, const mpm_variant *v, void *stream);
+
+/* mpm_scan followed by a wait on `stream` and a read of the total into
+ * *total (host). Returns EOVERFLOW when *total > capacity (the first
+ * `capacity` pairs are valid), ESTATE when the device flagged a failure.
+ * d_total is device scratch for one uint64 as in mpm_scan. */
+mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n,
+                         mpm_match *d_out, uint64_t capacity, void *d_work, uint64_t work_bytes,
+                         uint64_t *d_total, const mpm_variant *v, void *stream,
+                         uint64_t *total);
+
+/* ---------------------------------------------------------------------- */
+/* Scanning many texts in one replayable launch                            */
+/* ---------------------------------------------------------------------- */
+
+/* One request of a batch: one text scanned with one index under one variant.
+ * Output semantics per request are those of mpm_scan. */
+typedef struct {
+    const mpm_index *idx;
+    const uint8_t *d_text;
+    uint64_t n;
+    mpm_match *d_out;
+    uint64_t capacity;
+    uint64_t *d_total;
+    mpm_variant variant;
+} mpm_request;
+
+typedef struct mpm_batch mpm_batch;
+
+/* Plan a batch: requests sharing (index, variant) are grouped into one
+ * persistent launch whose workgroups take chunks of all the group's texts
+ * from a shared ticket counter, each text keeping its own ordered output.
+ * The plan copies the request array. Host-only.
+ * Errors: EINVAL, ETOOBIG, ENOMEM. */
+mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **out);
+
+/* Device bytes the plan needs (descriptor tables + workspace), and the upload
+ * of the descriptors into caller memory d_buf (256-byte aligned; zero-filled
+ * by the caller before first use). */
+uint64_t mpm_batch_device_bytes(const mpm_batch *b);
+mpm_status mpm_batch_upload(mpm_batch *b, void *d_buf, uint64_t bytes, void *stream);
+
+/* Enqueue every group launch of the plan on `stream` (no wait). */
+mpm_status mpm_batch_run(const mpm_batch *b, void *stream);
+
+/* Capture the plan's launches into a HIP graph once, then replay it with
+ * mpm_batch_replay (a single graph launch per batch). */
+mpm_status mpm_batch_capture(mpm_batch *b, void *stream);
+mpm_status mpm_batch_replay(const mpm_batch *b, void *stream);
+
+/* Number of group launches in the plan. */
+uint32_t mpm_batch_groups(const mpm_batch *b);
+
+void mpm_batch_free(mpm_batch *b);
+
+/* ---------------------------------------------------------------------- */
+/* Inspection (host-only; used by tests)                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Copy the dense Aho-Corasick table. Rows are states in breadth-first order
+ * (root 0; the d_unique depth-m states last, in ascending order of their
+ * pattern strings); columns are 1 + n_classes: column 0 (bytes in no pattern)
+ * leads to the root, column c to the state after the c-th smallest pattern
+ * byte. classes receives the n_classes bytes (may be NULL).
+ * table: n_states * (1 + n_classes) uint32 entries (may be NULL).
+ * Errors: EINVAL (not an AC index). */
+mpm_status mpm_export_ac(const mpm_index *idx, uint32_t *table, uint8_t *classes);
+
+/* Copy the Wu-Manber SHIFT table (4^B uint8 entries). Errors: EINVAL. */
+mpm_status mpm_export_wm_shift(const mpm_index *idx, uint8_t *shift);
+
+/* Copy the unique-string index: uoff (d_unique + 1 entries) and ids (d
+ * entries) so that ids[uoff[u] .. uoff[u+1]) are the ascending pattern ids of
+ * the u-th smallest distinct pattern string. Errors: EINVAL. */
+mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids);
+
+/* Last error message of this thread ("" if none). */
+const char *mpm_last_error(void);
+
+/* Library version string. */
+const char *mpm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_H */

@@ -1,0 +1,836 @@
+// Host side of the library: index builders, device-image packing and the
+// C-ABI entry points declared in include/mpm.h.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "mpm_internal.h"
+
+namespace mpm {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+mpm_status fail(mpm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Distinct pattern strings
+// ---------------------------------------------------------------------------
+// The Definition reports every pattern id, so equal patterns are kept as one
+// string with an ascending id list (the output set of a terminal state in
+// Algorithm 1 holds every pattern that ends there).
+static mpm_status dedup(const uint8_t *P, uint32_t d, uint32_t m, mpm_index *ix)
+{
+    std::vector<uint32_t> order(d);
+    std::iota(order.begin(), order.end(), 0u);
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        int c = memcmp(P + (uint64_t)a * m, P + (uint64_t)b * m, m);
+        return c != 0 ? c < 0 : a < b;
+    });
+    ix->uoff.clear();
+    ix->uids.resize(d);
+    ix->upats.clear();
+    ix->max_dup = 0;
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < d; k++) {
+        const uint8_t *p = P + (uint64_t)order[k] * m;
+        bool fresh = k == 0 || memcmp(p, P + (uint64_t)order[k - 1] * m, m) != 0;
+        if (fresh) {
+            if (k)
+                ix->max_dup = std::max(ix->max_dup, run);
+            run = 0;
+            ix->uoff.push_back(k);
+            ix->upats.insert(ix->upats.end(), p, p + m);
+        }
+        ix->uids[k] = order[k];
+        run++;
+    }
+    ix->max_dup = std::max(ix->max_dup, run);
+    ix->uoff.push_back(d);
+    ix->du = (uint32_t)(ix->uoff.size() - 1);
+    return MPM_OK;
+}
+
+template <typename T>
+static uint64_t put(std::vector<uint8_t> &img, const T *src, uint64_t count)
+{
+    uint64_t off = align_up(img.size(), 256);
+    uint64_t bytes = count * sizeof(T);
+    img.resize(align_up(off + bytes, 16), 0);
+    if (bytes)
+        memcpy(img.data() + off, src, bytes);
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// Aho-Corasick: trie (Algorithm 1), supply links in breadth-first order
+// (Algorithm 2), flattened transition table.
+// ---------------------------------------------------------------------------
+static mpm_status build_ac_tables(mpm_index *ix)
+{
+    const uint32_t m = ix->m, du = ix->du;
+    // Symbol classes: the distinct bytes of the patterns, ascending.
+    bool present[256] = {false};
+    for (uint8_t b : ix->upats)
+        present[b] = true;
+    uint32_t C = 0;
+    memset(ix->cls, 0, sizeof ix->cls);
+    for (int b = 0; b < 256; b++)
+        if (present[b]) {
+            ix->class_bytes[C] = (uint8_t)b;
+            ix->cls[b] = (uint8_t)(C + 1);
+            C++;
+        }
+    ix->n_classes = C;
+    const uint32_t cp = C + 1;
+
+    uint64_t max_nodes = (uint64_t)m * du + 1;
+    if (max_nodes > (1ull << 31))
+        return fail(MPM_ETOOBIG, "build_ac: up to %llu states exceed 2^31",
+                    (unsigned long long)max_nodes);
+
+    // Trie over the distinct strings in ascending order; nodes numbered in
+    // creation order (Algorithm 1).
+    std::vector<int32_t> child;
+    std::vector<uint32_t> depth;
+    child.reserve(std::min<uint64_t>(max_nodes, 1u << 22) * C);
+    child.assign(C, -1);
+    depth.push_back(0);
+    for (uint32_t u = 0; u < du; u++) {
+        const uint8_t *p = ix->upats.data() + (uint64_t)u * m;
+        int64_t q = 0;
+        for (uint32_t j = 0; j < m; j++) {
+            uint32_t c = ix->cls[p[j]] - 1;
+            int32_t nx = child[q * C + c];
+            if (nx < 0) {
+                nx = (int32_t)depth.size();
+                child[q * C + c] = nx;
+                child.resize(child.size() + C, -1);
+                depth.push_back(j + 1);
+            }
+            q = nx;
+        }
+    }
+    const uint64_t S = depth.size();
+
+    // Breadth-first order; children visited in ascending byte order, so each
+    // depth level is in lexicographic order of the state labels.
+    std::vector<uint32_t> order;
+    order.reserve(S);
+    order.push_back(0);
+    for (uint64_t h = 0; h < order.size(); h++) {
+        uint32_t v = order[h];
+        for (uint32_t c = 0; c < C; c++) {
+            int32_t w = child[(uint64_t)v * C + c];
+            if (w >= 0)
+                order.push_back((uint32_t)w);
+        }
+    }
+    std::vector<uint32_t> newid(S);
+    for (uint64_t k = 0; k < S; k++)
+        newid[order[k]] = (uint32_t)k;
+
+    // Supply (failure) links in breadth-first order (Algorithm 2): the supply
+    // state of w = g(v, c) is g(f, c) for the first f on v's supply chain
+    // that has a c-transition, else the root.
+    std::vector<uint32_t> supply(S, 0);
+    for (uint64_t h = 0; h < S; h++) {
+        uint32_t v = order[h];
+        for (uint32_t c = 0; c < C; c++) {
+            int32_t w = child[(uint64_t)v * C + c];
+            if (w < 0)
+                continue;
+            if (v == 0) {
+                supply[w] = 0;
+                continue;
+            }
+            uint32_t f = supply[v];
+            while (f != 0 && child[(uint64_t)f * C + c] < 0)
+                f = supply[f];
+            int32_t g = child[(uint64_t)f * C + c];
+            supply[w] = g >= 0 ? (uint32_t)g : 0;
+        }
+    }
+
+    // Flatten: delta(v, c) = g(v, c) if defined, else delta(supply(v), c),
+    // and the root's undefined transitions stay at the root. Supply states
+    // are shallower, so breadth-first order has them complete already.
+    std::vector<uint32_t> delta(S * C);
+    for (uint64_t h = 0; h < S; h++) {
+        uint32_t v = order[h];
+        for (uint32_t c = 0; c < C; c++) {
+            int32_t w = child[(uint64_t)v * C + c];
+            if (w >= 0)
+                delta[(uint64_t)v * C + c] = (uint32_t)w;
+            else
+                delta[(uint64_t)v * C + c] = v == 0 ? 0 : delta[(uint64_t)supply[v] * C + c];
+        }
+    }
+
+    // Table in breadth-first numbering with the "other byte" column 0.
+    ix->n_states = S;
+    ix->dfa.assign(S * cp, 0);
+    for (uint64_t k = 0; k < S; k++) {
+        uint32_t v = order[k];
+        for (uint32_t c = 0; c < C; c++)
+            ix->dfa[k * cp + 1 + c] = newid[delta[(uint64_t)v * C + c]];
+    }
+    // The deepest level holds exactly the distinct strings, in order.
+    uint64_t first_term = S - du;
+    for (uint64_t k = 0; k < S; k++) {
+        bool term = depth[order[k]] == m;
+        if (term != (k >= first_term))
+            return fail(MPM_EINVAL, "build_ac: internal error (terminal block)");
+    }
+    ix->state_bytes = S <= 65535 ? 2 : 4;
+
+    // Device image: table, class map, distinct-string CSR.
+    ix->image.clear();
+    if (ix->state_bytes == 2) {
+        std::vector<uint16_t> t16(ix->dfa.begin(), ix->dfa.end());
+        ix->off_a = put(ix->image, t16.data(), t16.size());
+    } else {
+        ix->off_a = put(ix->image, ix->dfa.data(), ix->dfa.size());
+    }
+    ix->table_bytes = align_up(S * cp * ix->state_bytes, 16);
+    ix->off_b = put(ix->image, ix->cls, 256);
+    ix->off_c = put(ix->image, ix->uoff.data(), ix->uoff.size());
+    ix->off_d = put(ix->image, ix->uids.data(), ix->uids.size());
+    ix->image.resize(align_up(ix->image.size(), 256), 0);
+    return MPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Wu-Manber tables (Algorithm 4) over 2-bit character codes.
+// ---------------------------------------------------------------------------
+static inline uint32_t wm_code(uint8_t c, uint32_t sh) { return (c >> sh) & 3u; }
+
+static inline uint32_t wm_block_hash(const uint8_t *p, uint32_t B, uint32_t sh)
+{
+    uint32_t h = 0;
+    for (uint32_t k = 0; k < B; k++)
+        h |= wm_code(p[k], sh) << (2 * k);
+    return h;
+}
+
+static void wm_tables(const mpm_index *ix, uint32_t B, uint32_t sh, std::vector<uint8_t> &shift,
+                      std::vector<uint32_t> &bcount)
+{
+    const uint32_t m = ix->m;
+    const uint32_t H = 1u << (2 * B);
+    shift.assign(H, (uint8_t)(m - B + 1));
+    bcount.assign(H, 0);
+    for (uint32_t u = 0; u < ix->du; u++) {
+        const uint8_t *p = ix->upats.data() + (uint64_t)u * m;
+        for (uint32_t q = B; q <= m; q++) {
+            // the block p_{q-B} .. p_{q-1}, m - q characters from the end
+            uint32_t h = wm_block_hash(p + q - B, B, sh);
+            uint8_t s = (uint8_t)(m - q);
+            if (s < shift[h])
+                shift[h] = s;
+            if (q == m)
+                bcount[h]++;
+        }
+    }
+}
+
+static double wm_cost(const std::vector<uint8_t> &shift, const std::vector<uint32_t> &bcount,
+                      uint32_t B)
+{
+    // Expected work per text byte for uniformly random block codes: windows
+    // visited per byte (1 / mean advance) times work per window (hash + probe,
+    // plus candidate checks when the shift is zero).
+    double adv = 0, work = 0;
+    const double H = (double)shift.size();
+    for (size_t h = 0; h < shift.size(); h++) {
+        adv += shift[h] ? shift[h] : 1;
+        work += 1.0 + 0.25 * B + (shift[h] == 0 ? 4.0 + 4.0 * bcount[h] : 0.0);
+    }
+    adv /= H;
+    work /= H;
+    return work / adv;
+}
+
+static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
+{
+    const uint32_t m = ix->m;
+    // Character code shift: the one that separates the most pattern bytes.
+    bool present[256] = {false};
+    for (uint8_t b : ix->upats)
+        present[b] = true;
+    uint32_t best_sh = 0, best_n = 0;
+    for (uint32_t sh = 0; sh < 6; sh++) {
+        bool seen[4] = {false};
+        uint32_t n = 0;
+        for (int b = 0; b < 256; b++)
+            if (present[b] && !seen[wm_code((uint8_t)b, sh)]) {
+                seen[wm_code((uint8_t)b, sh)] = true;
+                n++;
+            }
+        if (n > best_n) {
+            best_n = n;
+            best_sh = sh;
+        }
+    }
+    ix->code_shift = best_sh;
+    const uint32_t Bmax = std::min<uint32_t>(m, 8);
+    std::vector<uint8_t> shift;
+    std::vector<uint32_t> bcount;
+    uint32_t B = B_req;
+    if (B == 0) {
+        double best = 1e300;
+        for (uint32_t b = 1; b <= Bmax; b++) {
+            wm_tables(ix, b, best_sh, shift, bcount);
+            double c = wm_cost(shift, bcount, b);
+            if (c < best * 0.999) {
+                best = c;
+                B = b;
+            }
+        }
+    }
+    ix->B = B;
+    wm_tables(ix, B, best_sh, shift, bcount);
+    const uint32_t H = 1u << (2 * B);
+    ix->shift = shift;
+    ix->boff.assign(H + 1, 0);
+    for (uint32_t h = 0; h < H; h++)
+        ix->boff[h + 1] = ix->boff[h] + bcount[h];
+    ix->bu.assign(ix->boff[H], 0);
+    std::vector<uint32_t> fillp(ix->boff.begin(), ix->boff.end() - 1);
+    for (uint32_t u = 0; u < ix->du; u++) {  // ascending ranks per bucket
+        uint32_t h = wm_block_hash(ix->upats.data() + (uint64_t)u * m + m - B, B, best_sh);
+        ix->bu[fillp[h]++] = u;
+    }
+    ix->prefix.assign(ix->du, 0);
+    for (uint32_t u = 0; u < ix->du; u++) {
+        uint32_t key = 0;
+        for (uint32_t k = 0; k < std::min<uint32_t>(m, 4); k++)
+            key |= (uint32_t)ix->upats[(uint64_t)u * m + k] << (8 * k);
+        ix->prefix[u] = key;
+    }
+    double sum = 0;
+    uint32_t zeros = 0;
+    for (uint8_t s : shift) {
+        sum += s;
+        zeros += s == 0;
+    }
+    ix->mean_shift = sum / H;
+    ix->zero_shift = zeros;
+
+    ix->image.clear();
+    ix->off_a = put(ix->image, ix->shift.data(), ix->shift.size());
+    ix->table_bytes = align_up(H, 16);
+    ix->off_b = put(ix->image, ix->boff.data(), ix->boff.size());
+    ix->off_c = put(ix->image, ix->bu.data(), std::max<size_t>(ix->bu.size(), 1));
+    ix->off_d = put(ix->image, ix->prefix.data(), ix->prefix.size());
+    ix->off_e = put(ix->image, ix->upats.data(), ix->upats.size());
+    ix->off_f = put(ix->image, ix->uoff.data(), ix->uoff.size());
+    ix->off_g = put(ix->image, ix->uids.data(), ix->uids.size());
+    ix->image.resize(align_up(ix->image.size(), 256), 0);
+    return MPM_OK;
+}
+
+static mpm_status build_common(const uint8_t *P, uint32_t d, uint32_t m, mpm_index **out,
+                               const char *who)
+{
+    if (!out)
+        return fail(MPM_EINVAL, "%s: out is NULL", who);
+    *out = nullptr;
+    if (!P)
+        return fail(MPM_EINVAL, "%s: patterns is NULL", who);
+    if (d == 0)
+        return fail(MPM_EINVAL, "%s: d must be positive", who);
+    if (m == 0)
+        return fail(MPM_EINVAL, "%s: m must be positive", who);
+    if ((uint64_t)d * m > (1ull << 34))
+        return fail(MPM_ETOOBIG, "%s: pattern bytes exceed 16 GiB", who);
+    return MPM_OK;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+extern "C" {
+
+const char *mpm_last_error(void) { return g_err.c_str(); }
+const char *mpm_version(void) { return "mpm 1.0 (gfx950)"; }
+
+mpm_status mpm_build_ac(const uint8_t *patterns, uint32_t d, uint32_t m, const mpm_opts *opts,
+                        mpm_index **out)
+{
+    (void)opts;
+    mpm_status st = build_common(patterns, d, m, out, "mpm_build_ac");
+    if (st)
+        return st;
+    try {
+        mpm_index *ix = new mpm_index();
+        ix->algo = MPM_ALGO_AC;
+        ix->m = m;
+        ix->d = d;
+        dedup(patterns, d, m, ix);
+        st = build_ac_tables(ix);
+        if (st) {
+            delete ix;
+            return st;
+        }
+        *out = ix;
+        g_err.clear();
+        return MPM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPM_ENOMEM, "mpm_build_ac: out of host memory");
+    }
+}
+
+mpm_status mpm_build_wm(const uint8_t *patterns, uint32_t d, uint32_t m, const mpm_opts *opts,
+                        mpm_index **out)
+{
+    mpm_status st = build_common(patterns, d, m, out, "mpm_build_wm");
+    if (st)
+        return st;
+    uint32_t B = opts ? opts->wm_block : 0;
+    if (B != 0 && (B > m || B > 8))
+        return fail(MPM_EUNSUPPORTED, "mpm_build_wm: B=%u needs 1 <= B <= min(m=%u, 8)", B, m);
+    try {
+        mpm_index *ix = new mpm_index();
+        ix->algo = MPM_ALGO_WM;
+        ix->m = m;
+        ix->d = d;
+        dedup(patterns, d, m, ix);
+        st = build_wm_tables(ix, B);
+        if (st) {
+            delete ix;
+            return st;
+        }
+        *out = ix;
+        g_err.clear();
+        return MPM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPM_ENOMEM, "mpm_build_wm: out of host memory");
+    }
+}
+
+void mpm_free(mpm_index *idx) { delete idx; }
+
+uint64_t mpm_device_bytes(const mpm_index *idx) { return idx ? idx->image.size() : 0; }
+
+mpm_status mpm_upload(mpm_index *idx, void *d_buf, uint64_t bytes, void *stream)
+{
+    if (!idx || !d_buf)
+        return fail(MPM_EINVAL, "mpm_upload: null argument");
+    if (((uintptr_t)d_buf) & 255)
+        return fail(MPM_EINVAL, "mpm_upload: device buffer must be 256-byte aligned");
+    if (bytes < idx->image.size())
+        return fail(MPM_ENOMEM, "mpm_upload: buffer of %llu bytes, need %llu",
+                    (unsigned long long)bytes, (unsigned long long)idx->image.size());
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_buf, idx->image.data(), idx->image.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "mpm_upload: %s", hipGetErrorString(e));
+    idx->d_image = (const uint8_t *)d_buf;
+    g_err.clear();
+    return MPM_OK;
+}
+
+mpm_status mpm_index_info(const mpm_index *idx, mpm_info *o)
+{
+    if (!idx || !o)
+        return fail(MPM_EINVAL, "mpm_index_info: null argument");
+    memset(o, 0, sizeof *o);
+    o->algo = idx->algo;
+    o->m = idx->m;
+    o->d = idx->d;
+    o->d_unique = idx->du;
+    o->max_dup = idx->max_dup;
+    o->n_classes = idx->n_classes;
+    o->n_states = idx->n_states;
+    o->state_bytes = idx->state_bytes;
+    o->wm_block = idx->B;
+    o->wm_code_shift = idx->code_shift;
+    o->wm_zero_shift = idx->zero_shift;
+    o->wm_mean_shift = idx->mean_shift;
+    o->table_bytes = idx->table_bytes;
+    o->device_bytes = idx->image.size();
+    return MPM_OK;
+}
+
+mpm_status mpm_export_ac(const mpm_index *idx, uint32_t *table, uint8_t *classes)
+{
+    if (!idx || idx->algo != MPM_ALGO_AC)
+        return fail(MPM_EINVAL, "mpm_export_ac: not an Aho-Corasick index");
+    if (table)
+        memcpy(table, idx->dfa.data(), idx->dfa.size() * sizeof(uint32_t));
+    if (classes)
+        memcpy(classes, idx->class_bytes, idx->n_classes);
+    return MPM_OK;
+}
+
+mpm_status mpm_export_wm_shift(const mpm_index *idx, uint8_t *shift)
+{
+    if (!idx || idx->algo != MPM_ALGO_WM || !shift)
+        return fail(MPM_EINVAL, "mpm_export_wm_shift: not a Wu-Manber index");
+    memcpy(shift, idx->shift.data(), idx->shift.size());
+    return MPM_OK;
+}
+
+mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids)
+{
+    if (!idx)
+        return fail(MPM_EINVAL, "mpm_export_unique: null index");
+    if (uoff)
+        memcpy(uoff, idx->uoff.data(), idx->uoff.size() * sizeof(uint32_t));
+    if (ids)
+        memcpy(ids, idx->uids.data(), idx->uids.size() * sizeof(uint32_t));
+    return MPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Single-text scan
+// ---------------------------------------------------------------------------
+
+static uint64_t n_starts(uint64_t n, uint32_t m) { return n >= m ? n - m + 1 : 0; }
+
+mpm_status mpm_workspace_bytes(const mpm_index *idx, uint64_t n, const mpm_variant *v,
+                               uint64_t *bytes)
+{
+    if (!idx || !bytes)
+        return fail(MPM_EINVAL, "mpm_workspace_bytes: null argument");
+    LaunchCfg cfg;
+    mpm_status st = resolve_variant(idx, v, 0, &cfg);
+    if (st)
+        return st;
+    uint64_t tb = tile_bytes(cfg);
+    uint64_t nt = (n_starts(n, idx->m) + tb - 1) / tb;
+    *bytes = WS_HEADER_BYTES + 8 * nt;
+    return MPM_OK;
+}
+
+mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm_match *d_out,
+                    uint64_t capacity, void *d_work, uint64_t work_bytes, uint64_t *d_total,
+                    const mpm_variant *v, void *stream)
+{
+    if (!idx || !d_total || !d_work)
+        return fail(MPM_EINVAL, "mpm_scan: null index, workspace or total");
+    if (!idx->d_image)
+        return fail(MPM_ESTATE, "mpm_scan: index not uploaded (call mpm_upload)");
+    if (n >= (1ull << 32))
+        return fail(MPM_ETOOBIG, "mpm_scan: n = %llu needs 32-bit positions",
+                    (unsigned long long)n);
+    if (capacity && !d_out)
+        return fail(MPM_EINVAL, "mpm_scan: d_out is NULL with capacity > 0");
+    if (n && !d_text)
+        return fail(MPM_EINVAL, "mpm_scan: d_text is NULL");
+    if (((uintptr_t)d_work) & 7)
+        return fail(MPM_EINVAL, "mpm_scan: workspace must be 8-byte aligned");
+    LaunchCfg cfg;
+    uint64_t ns = n_starts(n, idx->m);
+    mpm_status st = resolve_variant(idx, v, 0, &cfg);
+    if (st)
+        return st;
+    uint64_t tb = tile_bytes(cfg);
+    uint64_t nt = (ns + tb - 1) / tb;
+    if (tb * (uint64_t)idx->max_dup >= (1ull << ST_VAL_BITS))
+        return fail(MPM_EUNSUPPORTED, "mpm_scan: %u copies of one pattern overflow a chunk count",
+                    idx->max_dup);
+    if (work_bytes < WS_HEADER_BYTES + 8 * nt)
+        return fail(MPM_ENOMEM, "mpm_scan: workspace of %llu bytes, need %llu",
+                    (unsigned long long)work_bytes, (unsigned long long)(WS_HEADER_BYTES + 8 * nt));
+    if (nt == 0)
+        return launch_zero_totals(nullptr, 0, d_total, stream);
+    st = resolve_variant(idx, v, nt, &cfg);
+    if (st)
+        return st;
+    ScanDev sd;
+    memset(&sd, 0, sizeof sd);
+    sd.single = TextDesc{d_text, n, d_out, capacity, d_total, 0, nt};
+    sd.multi = nullptr;
+    sd.ntexts = 1;
+    sd.lane_bytes = cfg.lane_bytes;
+    sd.ntiles = nt;
+    sd.hdr = (uint32_t *)d_work;
+    sd.status = (uint64_t *)((uint8_t *)d_work + WS_HEADER_BYTES);
+    return launch_scan(idx, cfg, sd, stream);
+}
+
+mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm_match *d_out,
+                         uint64_t capacity, void *d_work, uint64_t work_bytes, uint64_t *d_total,
+                         const mpm_variant *v, void *stream, uint64_t *total)
+{
+    if (!total)
+        return fail(MPM_EINVAL, "mpm_scan_sync: total is NULL");
+    mpm_status st = mpm_scan(idx, d_text, n, d_out, capacity, d_work, work_bytes, d_total, v, stream);
+    if (st)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t hdr[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(total, d_total, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hdr, d_work, sizeof hdr, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "mpm_scan_sync: %s", hipGetErrorString(e));
+    if (hdr[WS_ERR]) {
+        hipMemsetAsync((uint8_t *)d_work + 4 * WS_ERR, 0, 4, s);
+        hipStreamSynchronize(s);
+        return fail(MPM_ESTATE, "mpm_scan_sync: device look-back did not complete");
+    }
+    if (*total > capacity)
+        return fail(MPM_EOVERFLOW, "mpm_scan_sync: %llu matches, capacity %llu",
+                    (unsigned long long)*total, (unsigned long long)capacity);
+    g_err.clear();
+    return MPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct mpm_batch {
+    struct Group {
+        const mpm_index *idx;
+        mpm_variant var;
+        LaunchCfg cfg;
+        std::vector<TextDesc> texts;
+        uint64_t ntiles = 0;
+        uint64_t desc_off = 0, work_off = 0;
+    };
+    std::vector<mpm_request> reqs;
+    std::vector<Group> groups;
+    std::vector<uint64_t *> zero_totals;   // requests with no starting position
+    uint64_t zero_off = 0;
+    uint64_t bytes = 0;
+    uint8_t *d_buf = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **out)
+{
+    if (!out || (!reqs && count))
+        return fail(MPM_EINVAL, "mpm_batch_plan: null argument");
+    *out = nullptr;
+    try {
+        mpm_batch *b = new mpm_batch();
+        b->reqs.assign(reqs, reqs + count);
+        std::map<std::tuple<const mpm_index *, uint32_t, uint32_t, uint32_t, uint32_t>, size_t> key;
+        for (uint32_t k = 0; k < count; k++) {
+            const mpm_request &r = reqs[k];
+            if (!r.idx || !r.d_total || (r.n && !r.d_text) || (r.capacity && !r.d_out)) {
+                delete b;
+                return fail(MPM_EINVAL, "mpm_batch_plan: request %u has a null pointer", k);
+            }
+            if (r.n >= (1ull << 32)) {
+                delete b;
+                return fail(MPM_ETOOBIG, "mpm_batch_plan: request %u: n >= 2^32", k);
+            }
+            uint64_t ns = n_starts(r.n, r.idx->m);
+            if (ns == 0) {
+                b->zero_totals.push_back(r.d_total);
+                continue;
+            }
+            LaunchCfg cfg;
+            mpm_status st = resolve_variant(r.idx, &r.variant, 0, &cfg);
+            if (st) {
+                delete b;
+                return st;
+            }
+            auto kk = std::make_tuple(r.idx, cfg.lane_bytes, cfg.block_threads, cfg.placement,
+                                      r.variant.grid);
+            auto it = key.find(kk);
+            size_t gi;
+            if (it == key.end()) {
+                gi = b->groups.size();
+                key[kk] = gi;
+                mpm_batch::Group g;
+                g.idx = r.idx;
+                g.var = r.variant;
+                g.cfg = cfg;
+                b->groups.push_back(g);
+            } else {
+                gi = it->second;
+            }
+            mpm_batch::Group &g = b->groups[gi];
+            uint64_t tb = tile_bytes(g.cfg);
+            uint64_t nt = (ns + tb - 1) / tb;
+            if (tb * (uint64_t)r.idx->max_dup >= (1ull << ST_VAL_BITS)) {
+                delete b;
+                return fail(MPM_EUNSUPPORTED, "mpm_batch_plan: too many copies of one pattern");
+            }
+            g.texts.push_back(TextDesc{r.d_text, r.n, r.d_out, r.capacity, r.d_total, g.ntiles, nt});
+            g.ntiles += nt;
+        }
+        uint64_t off = 0;
+        for (auto &g : b->groups) {
+            mpm_status st = resolve_variant(g.idx, &g.var, g.ntiles, &g.cfg);
+            if (st) {
+                delete b;
+                return st;
+            }
+            g.desc_off = off;
+            off = align_up(off + g.texts.size() * sizeof(TextDesc), 256);
+            g.work_off = off;
+            off = align_up(off + WS_HEADER_BYTES + 8 * g.ntiles, 256);
+        }
+        b->zero_off = off;
+        off = align_up(off + 8 * b->zero_totals.size() + 8, 256);
+        b->bytes = off;
+        *out = b;
+        g_err.clear();
+        return MPM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPM_ENOMEM, "mpm_batch_plan: out of host memory");
+    }
+}
+
+uint64_t mpm_batch_device_bytes(const mpm_batch *b) { return b ? b->bytes : 0; }
+
+uint32_t mpm_batch_groups(const mpm_batch *b) { return b ? (uint32_t)b->groups.size() : 0; }
+
+mpm_status mpm_batch_upload(mpm_batch *b, void *d_buf, uint64_t bytes, void *stream)
+{
+    if (!b || !d_buf)
+        return fail(MPM_EINVAL, "mpm_batch_upload: null argument");
+    if (((uintptr_t)d_buf) & 255)
+        return fail(MPM_EINVAL, "mpm_batch_upload: buffer must be 256-byte aligned");
+    if (bytes < b->bytes)
+        return fail(MPM_ENOMEM, "mpm_batch_upload: buffer too small");
+    for (const auto &g : b->groups)
+        if (!g.idx->d_image)
+            return fail(MPM_ESTATE, "mpm_batch_upload: an index is not uploaded");
+    std::vector<uint8_t> host(b->bytes, 0);
+    for (const auto &g : b->groups)
+        memcpy(host.data() + g.desc_off, g.texts.data(), g.texts.size() * sizeof(TextDesc));
+    memcpy(host.data() + b->zero_off, b->zero_totals.data(), 8 * b->zero_totals.size());
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_buf, host.data(), b->bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "mpm_batch_upload: %s", hipGetErrorString(e));
+    b->d_buf = (uint8_t *)d_buf;
+    return MPM_OK;
+}
+
+mpm_status mpm_batch_run(const mpm_batch *b, void *stream)
+{
+    if (!b || !b->d_buf)
+        return fail(MPM_ESTATE, "mpm_batch_run: plan not uploaded");
+    if (!b->zero_totals.empty()) {
+        mpm_status st = launch_zero_totals((uint64_t *const *)(b->d_buf + b->zero_off),
+                                           (uint32_t)b->zero_totals.size(), nullptr, stream);
+        if (st)
+            return st;
+    }
+    for (const auto &g : b->groups) {
+        ScanDev sd;
+        memset(&sd, 0, sizeof sd);
+        if (g.texts.size() == 1) {
+            sd.single = g.texts[0];
+            sd.multi = nullptr;
+            sd.ntexts = 1;
+        } else {
+            sd.multi = (const TextDesc *)(b->d_buf + g.desc_off);
+            sd.ntexts = (uint32_t)g.texts.size();
+        }
+        sd.lane_bytes = g.cfg.lane_bytes;
+        sd.ntiles = g.ntiles;
+        sd.hdr = (uint32_t *)(b->d_buf + g.work_off);
+        sd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
+        mpm_status st = launch_scan(g.idx, g.cfg, sd, stream);
+        if (st)
+            return st;
+    }
+    return MPM_OK;
+}
+
+mpm_status mpm_batch_capture(mpm_batch *b, void *stream)
+{
+    if (!b || !b->d_buf)
+        return fail(MPM_ESTATE, "mpm_batch_capture: plan not uploaded");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "mpm_batch_capture: begin: %s", hipGetErrorString(e));
+    mpm_status st = mpm_batch_run(b, stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (st) {
+        if (g)
+            hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "mpm_batch_capture: end: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(MPM_EHIP, "mpm_batch_capture: instantiate: %s", hipGetErrorString(e));
+    }
+    b->graph = g;
+    return MPM_OK;
+}
+
+mpm_status mpm_batch_replay(const mpm_batch *b, void *stream)
+{
+    if (!b || !b->exec)
+        return fail(MPM_ESTATE, "mpm_batch_replay: no captured graph");
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "mpm_batch_replay: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+void mpm_batch_free(mpm_batch *b)
+{
+    if (!b)
+        return;
+    if (b->exec)
+        hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        hipGraphDestroy(b->graph);
+    delete b;
+}
+
+}  // extern "C"

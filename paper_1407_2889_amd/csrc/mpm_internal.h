@@ -1,0 +1,138 @@
+// Internal declarations shared by the host builders (mpm_host.cpp) and the
+// scan kernels (mpm_scan.hip). Not part of the public interface.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mpm.h"
+
+namespace mpm {
+
+// ---------------------------------------------------------------------------
+// Kernel-argument descriptors (passed by value)
+// ---------------------------------------------------------------------------
+
+// Dense Aho-Corasick table. Row s holds `cp` entries: column 0 is the class of
+// bytes that occur in no pattern (always leads to the root), columns 1..cp-1
+// the pattern bytes in ascending order. States are numbered breadth-first, so
+// the depth-m states (one per distinct pattern string, in ascending string
+// order) are the last `n_unique` rows: state s is terminal iff
+// s >= first_term, and then u = s - first_term is the string's rank.
+struct AcDev {
+    const void *dfa;        // uint16 or uint32 entries
+    const uint8_t *cls;     // 256 entries: column per byte value
+    const uint32_t *uoff;   // n_unique + 1: CSR offsets into uids
+    const uint32_t *uids;   // d: ascending pattern ids per distinct string
+    uint32_t n_states;
+    uint32_t first_term;
+    uint32_t cp;            // columns per row
+    uint32_t m;
+    uint32_t dfa_bytes;     // bytes of the table (multiple of 16)
+    uint32_t dupfree;       // every distinct string has exactly one id
+};
+
+// Wu-Manber tables. A block of B characters hashes to
+// sum_k ((c_k >> code_shift) & 3) << 2k (first character in the low bits).
+struct WmDev {
+    const uint8_t *shift;   // 4^B entries
+    const uint32_t *boff;   // 4^B + 1 CSR offsets into bu
+    const uint32_t *bu;     // distinct-string ranks whose last block hashes to h, ascending
+    const uint32_t *prefix; // per distinct string: its first min(m, 4) bytes, little-endian
+    const uint8_t *pats;    // distinct strings, n_unique * m bytes, ascending
+    const uint32_t *uoff;
+    const uint32_t *uids;
+    uint32_t B;
+    uint32_t code_shift;
+    uint32_t m;
+    uint32_t shift_bytes;   // 4^B rounded up to 16
+    uint32_t dupfree;
+};
+
+// One text of a launch. Tiles of a launch are numbered globally; a text
+// owns tiles [tile_begin, tile_begin + ntiles).
+struct TextDesc {
+    const uint8_t *text;
+    uint64_t n;
+    mpm_match *out;
+    uint64_t cap;
+    uint64_t *total;
+    uint64_t tile_begin;
+    uint64_t ntiles;
+};
+
+// Workspace header words (uint32): ticket counter, finished-workgroup
+// counter, launch epoch, device error flag. Followed (at byte 64) by one
+// uint64 look-back status word per tile.
+enum { WS_TICKET = 0, WS_DONE = 1, WS_EPOCH = 2, WS_ERR = 3 };
+static const uint64_t WS_HEADER_BYTES = 64;
+
+struct ScanDev {
+    TextDesc single;          // used when ntexts == 1
+    const TextDesc *multi;    // device array when ntexts > 1
+    uint32_t ntexts;
+    uint32_t lane_bytes;
+    uint64_t ntiles;
+    uint32_t *hdr;
+    uint64_t *status;
+};
+
+// Look-back status word: [63:38] epoch, [37:36] flag, [35:0] value.
+static const uint64_t ST_VAL_BITS = 36;
+static const uint64_t ST_VAL_MASK = (1ull << ST_VAL_BITS) - 1;
+static const uint32_t ST_EPOCH_MASK = (1u << 26) - 1;
+
+}  // namespace mpm
+
+// ---------------------------------------------------------------------------
+// Host-side index
+// ---------------------------------------------------------------------------
+struct mpm_index {
+    uint32_t algo = 0;
+    uint32_t m = 0, d = 0, du = 0, max_dup = 0;
+    std::vector<uint32_t> uoff, uids;   // distinct strings -> ids
+    std::vector<uint8_t> upats;         // du * m, ascending strings
+
+    // Aho-Corasick
+    uint32_t n_classes = 0;
+    uint8_t class_bytes[256] = {0};
+    uint8_t cls[256] = {0};
+    uint64_t n_states = 0;
+    uint32_t state_bytes = 0;
+    std::vector<uint32_t> dfa;          // n_states * (1 + n_classes)
+
+    // Wu-Manber
+    uint32_t B = 0, code_shift = 0, zero_shift = 0;
+    double mean_shift = 0;
+    std::vector<uint8_t> shift;
+    std::vector<uint32_t> boff, bu, prefix;
+
+    // Device image: host copy, offsets, and the caller-owned device buffer.
+    std::vector<uint8_t> image;
+    uint64_t off_a = 0, off_b = 0, off_c = 0, off_d = 0, off_e = 0, off_f = 0, off_g = 0;
+    uint64_t table_bytes = 0;
+    const uint8_t *d_image = nullptr;
+};
+
+namespace mpm {
+void set_error(const char *fmt, ...);
+mpm_status fail(mpm_status st, const char *fmt, ...);
+
+// Launch the scan kernels (mpm_scan.hip).
+struct LaunchCfg {
+    uint32_t lane_bytes;
+    uint32_t block_threads;
+    uint32_t placement;   // resolved: LDS or GLOBAL
+    uint32_t grid;        // resolved workgroup count
+    uint32_t lds_bytes;   // dynamic LDS per workgroup
+};
+mpm_status resolve_variant(const mpm_index *idx, const mpm_variant *v, uint64_t ntiles_hint,
+                           LaunchCfg *cfg);
+uint64_t tile_bytes(const LaunchCfg &cfg);
+mpm_status launch_scan(const mpm_index *idx, const LaunchCfg &cfg, const ScanDev &sd,
+                       void *stream);
+mpm_status launch_zero_totals(uint64_t *const *d_totals_dev, uint32_t count, uint64_t *single,
+                              void *stream);
+}  // namespace mpm

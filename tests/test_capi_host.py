@@ -1,0 +1,169 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side builders produce tables whose behaviour matches the oracle
+(simulated on the CPU from the exported tables; no GPU involved)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1407_2889_amd as mpm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "mpm.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mpm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert "mpm_build_ac" in syms and "mpm_scan" in syms and "mpm_free" in syms
+    lib = C.CDLL(mpm.LIB_PATH)
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(mpm.EXPORTS)
+    assert mpm._L.mpm_version().startswith(b"mpm")
+
+
+def test_error_codes():
+    P = np.frombuffer(b"ACGTACGT", np.uint8).reshape(2, 4)
+    h = C.c_void_p()
+    assert mpm._L.mpm_build_ac(P.ctypes.data, 0, 4, None, C.byref(h)) == mpm.MPM_EINVAL
+    assert b"d must be positive" in mpm._L.mpm_last_error()
+    assert mpm._L.mpm_build_ac(P.ctypes.data, 2, 0, None, C.byref(h)) == mpm.MPM_EINVAL
+    assert mpm._L.mpm_build_ac(None, 2, 4, None, C.byref(h)) == mpm.MPM_EINVAL
+    assert mpm._L.mpm_build_wm(P.ctypes.data, 2, 4, None, None) == mpm.MPM_EINVAL
+    o = mpm.Opts()
+    o.wm_block = 5
+    assert mpm._L.mpm_build_wm(P.ctypes.data, 2, 4, C.byref(o), C.byref(h)) == mpm.MPM_EUNSUPPORTED
+    o.wm_block = 9
+    P9 = np.zeros((1, 12), np.uint8)
+    assert mpm._L.mpm_build_wm(P9.ctypes.data, 1, 12, C.byref(o), C.byref(h)) == mpm.MPM_EUNSUPPORTED
+    mpm._L.mpm_free(None)  # NULL-safe
+    # scanning an index that was never uploaded
+    ix = mpm.build_ac(P)
+    tot = C.c_uint64()
+    st = mpm._L.mpm_scan_sync(ix.handle, C.c_void_p(16), 8, None, 0, C.c_void_p(64), 1 << 20,
+                              C.c_void_p(8), None, None, C.byref(tot))
+    assert st == mpm.MPM_ESTATE
+    with pytest.raises(mpm.MpmError):
+        mpm.workspace_bytes(ix, 100, mpm.variant(lane_bytes=24))
+    with pytest.raises(mpm.MpmError):
+        mpm.workspace_bytes(ix, 100, mpm.variant(block_threads=128))
+
+
+def simulate_dfa(table, classes, m, du, text):
+    """Walk the exported dense table on the CPU: column 0 for bytes in no
+    pattern, column k for the k-th smallest pattern byte."""
+    col = np.zeros(256, np.int64)
+    for k, b in enumerate(classes):
+        col[b] = k + 1
+    S = table.shape[0]
+    first = S - du
+    s = 0
+    hits = []
+    for i, b in enumerate(np.asarray(text, np.uint8)):
+        s = int(table[s, col[b]])
+        if s >= first:
+            hits.append((i - m + 1, s - first))
+    return hits
+
+
+def expand(hits, uoff, ids):
+    out = []
+    for pos, u in hits:
+        for j in range(uoff[u], uoff[u + 1]):
+            out.append((pos, int(ids[j])))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(25))
+def test_ac_table_walk_equals_oracle(seed):
+    rng = np.random.default_rng(seed)
+    alpha = np.frombuffer(b"ACGTN\n" if seed % 2 else b"ACGT", np.uint8)
+    m = int(rng.integers(1, 9))
+    d = int(rng.integers(1, 40))
+    T = alpha[rng.integers(0, len(alpha), 3000)]
+    P = alpha[rng.integers(0, len(alpha), (d, m))]
+    if d > 3:
+        P[1] = P[0]
+        P[2] = T[10:10 + m]
+    ix = mpm.build_ac(P)
+    inf = ix.info()
+    table, classes = ix.export_ac()
+    uoff, ids = ix.export_unique()
+    assert inf["d_unique"] == len({bytes(p) for p in P})
+    assert list(classes) == sorted(set(P.flatten().tolist()))
+    # column 0 always returns to the root; terminals are the last block
+    assert (table[:, 0] == 0).all()
+    assert inf["n_states"] == table.shape[0]
+    got = expand(simulate_dfa(table, classes, m, inf["d_unique"], T), uoff, ids)
+    pos, idv = oracle.Win(P).scan(T)
+    assert got == list(zip(pos.tolist(), idv.tolist()))
+
+
+def test_ac_state_count_matches_oracle_trie():
+    rng = np.random.default_rng(3)
+    P = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, (300, 8))]
+    ix = mpm.build_ac(P)
+    assert ix.info()["n_states"] == oracle.AC(P).nstates
+    assert ix.info()["state_bytes"] == 2
+
+
+def test_unique_csr():
+    P = np.frombuffer(b"CCAAGGAACC", np.uint8).reshape(5, 2)   # CC AA GG AA CC
+    ix = mpm.build_ac(P)
+    uoff, ids = ix.export_unique()
+    assert uoff.tolist() == [0, 2, 4, 5]      # AA:{1,3} CC:{0,4} GG:{2}
+    assert ids.tolist() == [1, 3, 0, 4, 2]
+    assert ix.info()["max_dup"] == 2
+
+
+def wm_hash2(block, sh):
+    h = 0
+    for k, c in enumerate(block):
+        h |= ((c >> sh) & 3) << (2 * k)
+    return h
+
+
+@pytest.mark.parametrize("B", [0, 1, 2, 3, 5, 8])
+def test_wm_shift_table_definition(B):
+    rng = np.random.default_rng(B + 10)
+    m = 12
+    P = np.frombuffer(b"ACGTN", np.uint8)[rng.integers(0, 5, (60, m))]
+    ix = mpm.build_wm(P, B=B)
+    inf = ix.info()
+    B = inf["wm_block"]
+    sh = inf["wm_code_shift"]
+    table = ix.export_wm_shift()
+    assert table.size == 4 ** B
+    best = {}
+    for p in P:
+        for q in range(B, m + 1):
+            h = wm_hash2(bytes(p[q - B:q]), sh)
+            best[h] = min(best.get(h, m - B + 1), m - q)
+    for h in range(4 ** B):
+        assert table[h] == best.get(h, m - B + 1)
+    assert inf["wm_zero_shift"] == int((table == 0).sum())
+
+
+def test_wm_code_shift_separates_dna():
+    P = np.frombuffer(b"ACGTACGTACGTGGCC", np.uint8).reshape(2, 8)
+    inf = mpm.build_wm(P).info()
+    codes = {(c >> inf["wm_code_shift"]) & 3 for c in b"ACGT"}
+    assert len(codes) == 4
+
+
+def test_wm_auto_block_prefers_long_blocks_for_sparse_sets():
+    rng = np.random.default_rng(0)
+    P = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, (1000, 16))]
+    inf = mpm.build_wm(P).info()
+    assert inf["wm_block"] >= 6
+    assert inf["wm_mean_shift"] > 5

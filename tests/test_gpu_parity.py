@@ -1,0 +1,185 @@
+"""GPU parity: the HIP scan through the C-ABI against the CPU oracle,
+element by element (bit-exact (pos, id) lists)."""
+
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mpm():
+    import paper_1407_2889_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def to_dev(text: np.ndarray, misalign: int = 0):
+    """Device copy of text starting `misalign` bytes into a 256-aligned buffer."""
+    buf = torch.zeros(len(text) + misalign + 64, dtype=torch.uint8, device="cuda")
+    if len(text):
+        buf[misalign:misalign + len(text)] = torch.from_numpy(np.ascontiguousarray(text)).cuda()
+    return buf[misalign:misalign + len(text)]
+
+
+def gpu_pairs(mpm, ix, text, var=None, misalign=0, capacity=None):
+    t = to_dev(text, misalign)
+    out = mpm.scan(ix, t, capacity=capacity, var=var)
+    return mpm.pairs_numpy(out)
+
+
+def assert_same(got, want, what=""):
+    gp, gi = got
+    wp, wi = want
+    assert len(gp) == len(wp), f"{what}: {len(gp)} pairs vs oracle {len(wp)}"
+    if len(wp):
+        bad = np.nonzero((gp != wp) | (gi != wi))[0]
+        assert bad.size == 0, f"{what}: first mismatch at {bad[0]}: got {(gp[bad[0]], gi[bad[0]])} want {(wp[bad[0]], wi[bad[0]])}"
+
+
+VARIANTS = [dict(lane_bytes=L, block_threads=W, placement=P)
+            for L, W, P in itertools.product((16, 64, 256), (256, 512, 1024), (1, 2))]
+
+
+@pytest.fixture(scope="module")
+def small():
+    text, ps = synth.workload_small()
+    want = oracle.parallel_scan(oracle.Win(ps.patterns), text)
+    return text, ps.patterns, want
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_small_workload_all_variants(mpm, small, algo):
+    text, P, want = small
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    for v in VARIANTS:
+        if algo == "wm" and v["lane_bytes"] * v["block_threads"] > 128 * 1024:
+            # the chunk's text is staged in LDS: such chunks are rejected
+            with pytest.raises(mpm.MpmError):
+                mpm.workspace_bytes(ix, len(text), mpm.variant(**v))
+            continue
+        say(f"[small 1MiB d=100 m=8] {algo} {v}")
+        got = gpu_pairs(mpm, ix, text, mpm.variant(**v))
+        assert_same(got, want, f"{algo} {v}")
+    assert len(want[0]) > 800
+
+
+def edge_cases():
+    rng = np.random.default_rng(11)
+    acgt = np.frombuffer(b"ACGT", np.uint8)
+    cases = []
+    cases.append(("empty", np.zeros(0, np.uint8), acgt[rng.integers(0, 4, (5, 4))]))
+    cases.append(("n<m", acgt[rng.integers(0, 4, 3)], acgt[rng.integers(0, 4, (5, 4))]))
+    t = acgt[rng.integers(0, 4, 8)]
+    cases.append(("n==m", t, np.stack([t, t, acgt[rng.integers(0, 4, 8)]])))
+    t = acgt[rng.integers(0, 4, 100_003)]
+    P = acgt[rng.integers(0, 4, (64, 6))]
+    P[:20] = np.stack([t[s:s + 6] for s in rng.integers(0, len(t) - 6, 20)])
+    cases.append(("ragged", t, P))
+    cases.append(("all-A dense", np.full(70_001, ord("A"), np.uint8),
+                  np.full((3, 5), ord("A"), np.uint8)))
+    t = np.frombuffer(b"ACGT\n", np.uint8)[rng.integers(0, 5, 50_000)]
+    cases.append(("newline-dense", t, acgt[rng.integers(0, 4, (200, 3))]))
+    t = acgt[rng.integers(0, 4, 30_000)]
+    P = acgt[rng.integers(0, 4, (50, 4))]
+    P[10:30] = P[0]
+    P[0] = t[100:104]
+    cases.append(("duplicates", t, P))
+    cases.append(("m=1", acgt[rng.integers(0, 4, 20_000)], np.frombuffer(b"ACX", np.uint8).reshape(3, 1)))
+    t = synth.est_text(200_000, seed=5)
+    ps = synth.pattern_set(t, d=300, m=32, n_planted=150, seed=6)
+    cases.append(("m=32 est", t, ps.patterns))
+    t = synth.est_text(150_000, seed=7)
+    ps = synth.pattern_set(t, d=5000, m=8, n_planted=2500, seed=8)
+    cases.append(("m=8 d=5000 dense", t, ps.patterns))
+    bytes_all = rng.integers(0, 256, 40_000).astype(np.uint8)
+    P = np.stack([bytes_all[s:s + 5] for s in rng.integers(0, 40_000 - 5, 30)])
+    cases.append(("binary alphabet", bytes_all, P))
+    return cases
+
+
+@pytest.mark.parametrize("case", edge_cases(), ids=lambda c: c[0])
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_edge_cases(mpm, case, algo):
+    name, T, P = case
+    want = oracle.Win(P).scan(T)
+    assert_same(oracle.AC(P).scan(T), want, "oracle AC")
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    for mis in (0, 3):
+        for v in (dict(lane_bytes=16, block_threads=256), dict(lane_bytes=64, block_threads=1024),
+                  dict(lane_bytes=256, block_threads=512, placement=2)):
+            say(f"[edge {name} n={len(T)} d={len(P)} m={P.shape[1]}] {algo} misalign={mis} {v}")
+            got = gpu_pairs(mpm, ix, T, mpm.variant(**v), misalign=mis)
+            assert_same(got, want, f"{name} {algo} mis={mis} {v}")
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_capacity_overflow_keeps_sorted_prefix(mpm, small, algo):
+    text, P, want = small
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    t = to_dev(text)
+    cap = len(want[0]) // 3
+    say(f"[overflow] {algo} cap={cap}")
+    sc = mpm.Scanner(ix, len(text), cap)
+    with pytest.raises(mpm.MpmError) as e:
+        sc.scan(t)
+    assert e.value.status == mpm.MPM_EOVERFLOW
+    got = mpm.pairs_numpy(sc.out[:cap])
+    assert_same(got, (want[0][:cap], want[1][:cap]), "prefix")
+    assert int(sc.total.item()) == len(want[0])
+    # capacity 0: count only
+    sc0 = mpm.Scanner(ix, len(text), 0)
+    with pytest.raises(mpm.MpmError):
+        sc0.scan(t)
+    assert int(sc0.total.item()) == len(want[0])
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_repeat_determinism_and_workspace_reuse(mpm, small, algo):
+    text, P, want = small
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    t = to_dev(text)
+    for v in (mpm.variant(lane_bytes=16, block_threads=256, grid=7),
+              mpm.variant(lane_bytes=64, block_threads=1024)):
+        sc = mpm.Scanner(ix, len(text), len(want[0]) + 10, v)
+        for rep in range(6):
+            say(f"[repeat] {algo} {v} rep={rep}")
+            got = mpm.pairs_numpy(sc.scan(t))
+            assert_same(got, want, f"rep {rep}")
+        # shorter text through the same workspace
+        got = mpm.pairs_numpy(sc.scan(t[:100_000]))
+        w2 = oracle.Win(P).scan(text[:100_000])
+        assert_same(got, w2, "prefix text")
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_est256_full_list(mpm, algo):
+    """The 256 MiB EST-shaped text, d=1000, m=16, full match list, in the
+    launch configuration the benchmark times."""
+    import bench
+    say(f"[est256] generating")
+    text, ps = synth.workload_est256()
+    want = oracle.parallel_scan(oracle.Win(ps.patterns), text)
+    assert len(want[0]) >= 300
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(ps.patterns, upload=True)
+    v = bench.DEFAULT_VARIANTS[algo]
+    say(f"[est256] {algo} {v}")
+    got = gpu_pairs(mpm, ix, text, mpm.variant(**v))
+    assert_same(got, want, f"est256 {algo}")
+    # planted patterns all occur at their recorded starts
+    found = set(zip(got[0].tolist(), got[1].tolist()))
+    for r, s in enumerate(ps.planted_starts.tolist()):
+        assert (s, r) in found
