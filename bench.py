@@ -27,8 +27,8 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, 8 TB/s
 
 DEFAULT_VARIANTS = {
-    "ac": dict(lane_bytes=128, block_threads=1024, placement=0),
-    "wm": dict(lane_bytes=64, block_threads=256, placement=0),
+    "ac": dict(lane_bytes=1024, block_threads=1024, placement=0),
+    "wm": dict(lane_bytes=1024, block_threads=1024, placement=0),
 }
 
 METRIC = "text GB/s scanned (AC, WM) + %HBM roofline; learned vs exhaustive-tuned GB/s"

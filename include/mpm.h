@@ -85,7 +85,13 @@ typedef struct {
     uint32_t block_threads;  /* 256, 512 or 1024 (default 256) */
     uint32_t placement;      /* MPM_PLACE_* */
     uint32_t grid;           /* workgroups launched; 0 = enough to fill the device */
+    uint32_t flags;          /* MPM_VARIANT_* bits */
 } mpm_variant;
+
+/* Aho-Corasick normally maps text bytes to table columns in registers when
+ * the pattern bytes have distinct 3-bit codes; this flag forces the byte ->
+ * column lookup table in LDS instead. */
+#define MPM_VARIANT_NO_SWAR 1u
 
 /* Facts about a built index. */
 typedef struct {

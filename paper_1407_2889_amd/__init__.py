@@ -49,16 +49,19 @@ class Opts(C.Structure):
     _fields_ = [("wm_block", C.c_uint32), ("reserved", C.c_uint32 * 7)]
 
 
+VARIANT_NO_SWAR = 1
+
+
 class Variant(C.Structure):
     _fields_ = [("lane_bytes", C.c_uint32), ("block_threads", C.c_uint32),
-                ("placement", C.c_uint32), ("grid", C.c_uint32)]
+                ("placement", C.c_uint32), ("grid", C.c_uint32), ("flags", C.c_uint32)]
 
     def __repr__(self):
         return (f"Variant(lane_bytes={self.lane_bytes}, block_threads={self.block_threads}, "
-                f"placement={self.placement}, grid={self.grid})")
+                f"placement={self.placement}, grid={self.grid}, flags={self.flags})")
 
     def key(self):
-        return (self.lane_bytes, self.block_threads, self.placement, self.grid)
+        return (self.lane_bytes, self.block_threads, self.placement, self.grid, self.flags)
 
 
 class Info(C.Structure):
@@ -140,8 +143,8 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def variant(lane_bytes=0, block_threads=0, placement=PLACE_AUTO, grid=0) -> Variant:
-    return Variant(lane_bytes, block_threads, placement, grid)
+def variant(lane_bytes=0, block_threads=0, placement=PLACE_AUTO, grid=0, flags=0) -> Variant:
+    return Variant(lane_bytes, block_threads, placement, grid, flags)
 
 
 def _patterns_np(patterns) -> np.ndarray:

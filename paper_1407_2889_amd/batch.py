@@ -66,7 +66,7 @@ class BatchScan:
             r.capacity = int(self.caps[i])
             r.d_total = base_tot + 8 * i
             v = variants[i]
-            r.variant = Variant(v.lane_bytes, v.block_threads, v.placement, v.grid)
+            r.variant = Variant(v.lane_bytes, v.block_threads, v.placement, v.grid, v.flags)
         h = C.c_void_p()
         _check(_L.mpm_batch_plan(reqs, self.count, C.byref(h)), "mpm_batch_plan")
         self._h = h

@@ -210,6 +210,9 @@ static mpm_status build_ac_tables(mpm_index *ix)
             return fail(MPM_EINVAL, "build_ac: internal error (terminal block)");
     }
     ix->state_bytes = S <= 65535 ? 2 : 4;
+    if (S * cp * ix->state_bytes >= (1ull << 32))
+        return fail(MPM_ETOOBIG, "build_ac: table of %llu states x %u columns exceeds 4 GiB",
+                    (unsigned long long)S, cp);
 
     // Device image: table, class map, distinct-string CSR.
     ix->image.clear();
@@ -220,7 +223,39 @@ static mpm_status build_ac_tables(mpm_index *ix)
         ix->off_a = put(ix->image, ix->dfa.data(), ix->dfa.size());
     }
     ix->table_bytes = align_up(S * cp * ix->state_bytes, 16);
-    ix->off_b = put(ix->image, ix->cls, 256);
+    // Column byte offsets per byte value, and the table-free class codes.
+    uint16_t cls_off[256];
+    for (int b = 0; b < 256; b++)
+        cls_off[b] = (uint16_t)(ix->cls[b] * ix->state_bytes);
+    ix->off_b = put(ix->image, cls_off, 256);
+    ix->swar_ok = 0;
+    if (C <= 7 && ix->state_bytes * C <= 255) {
+        for (uint32_t sh = 0; sh < 6 && !ix->swar_ok; sh++) {
+            int owner[8];
+            for (int k = 0; k < 8; k++)
+                owner[k] = -1;
+            bool ok = true;
+            for (uint32_t c = 0; c < C && ok; c++) {
+                int code = (ix->class_bytes[c] >> sh) & 7;
+                if (owner[code] >= 0)
+                    ok = false;
+                owner[code] = (int)c;
+            }
+            if (!ok)
+                continue;
+            ix->swar_ok = 1;
+            ix->swar_shift = sh;
+            for (int k = 0; k < 8; k++) {
+                if (owner[k] >= 0) {
+                    ix->perm_byte[k] = ix->class_bytes[owner[k]];
+                    ix->perm_col[k] = (uint8_t)((owner[k] + 1) * ix->state_bytes);
+                } else {
+                    ix->perm_byte[k] = (uint8_t)(((k + 1) & 7) << sh);  // has another code
+                    ix->perm_col[k] = 0;
+                }
+            }
+        }
+    }
     ix->off_c = put(ix->image, ix->uoff.data(), ix->uoff.size());
     ix->off_d = put(ix->image, ix->uids.data(), ix->uids.size());
     ix->image.resize(align_up(ix->image.size(), 256), 0);
@@ -262,16 +297,17 @@ static void wm_tables(const mpm_index *ix, uint32_t B, uint32_t sh, std::vector<
 }
 
 static double wm_cost(const std::vector<uint8_t> &shift, const std::vector<uint32_t> &bcount,
-                      uint32_t B)
+                      uint32_t /*B*/)
 {
     // Expected work per text byte for uniformly random block codes: windows
-    // visited per byte (1 / mean advance) times work per window (hash + probe,
-    // plus candidate checks when the shift is zero).
+    // visited per byte (1 / mean advance) times work per window. The scan
+    // reads each block hash out of a register history, so a window costs the
+    // same for every B; a zero shift adds the bucket walk.
     double adv = 0, work = 0;
     const double H = (double)shift.size();
     for (size_t h = 0; h < shift.size(); h++) {
         adv += shift[h] ? shift[h] : 1;
-        work += 1.0 + 0.25 * B + (shift[h] == 0 ? 4.0 + 4.0 * bcount[h] : 0.0);
+        work += 1.0 + (shift[h] == 0 ? 1.0 + 0.5 * bcount[h] : 0.0);
     }
     adv /= H;
     work /= H;
@@ -281,26 +317,32 @@ static double wm_cost(const std::vector<uint8_t> &shift, const std::vector<uint3
 static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
 {
     const uint32_t m = ix->m;
-    // Character code shift: the one that separates the most pattern bytes.
-    bool present[256] = {false};
+    // Character code shift: the one under which two random pattern
+    // characters collide least often (sum over codes of the squared share of
+    // pattern characters with that code), so frequent bytes get codes of
+    // their own.
+    double freq[256] = {0};
     for (uint8_t b : ix->upats)
-        present[b] = true;
-    uint32_t best_sh = 0, best_n = 0;
+        freq[b] += 1.0;
+    uint32_t best_sh = 0;
+    double best_c = 1e300;
     for (uint32_t sh = 0; sh < 6; sh++) {
-        bool seen[4] = {false};
-        uint32_t n = 0;
+        double mass[4] = {0, 0, 0, 0};
         for (int b = 0; b < 256; b++)
-            if (present[b] && !seen[wm_code((uint8_t)b, sh)]) {
-                seen[wm_code((uint8_t)b, sh)] = true;
-                n++;
-            }
-        if (n > best_n) {
-            best_n = n;
+            mass[wm_code((uint8_t)b, sh)] += freq[b];
+        const double c = mass[0] * mass[0] + mass[1] * mass[1] + mass[2] * mass[2] + mass[3] * mass[3];
+        if (c < best_c * (1 - 1e-12)) {
+            best_c = c;
             best_sh = sh;
         }
     }
     ix->code_shift = best_sh;
-    const uint32_t Bmax = std::min<uint32_t>(m, 8);
+    // Zero-shift hashes carry a 15-bit bucket number, so B = 8 is used only
+    // when fewer than 2^15 distinct strings exist.
+    const uint32_t Bmax = std::min<uint32_t>(std::min<uint32_t>(m, 8), ix->du < 32768 ? 8 : 7);
+    if (B_req > Bmax)
+        return fail(MPM_EUNSUPPORTED, "mpm_build_wm: B=%u exceeds %u for m=%u, %u strings", B_req,
+                    Bmax, m, ix->du);
     std::vector<uint8_t> shift;
     std::vector<uint32_t> bcount;
     uint32_t B = B_req;
@@ -319,37 +361,55 @@ static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
     wm_tables(ix, B, best_sh, shift, bcount);
     const uint32_t H = 1u << (2 * B);
     ix->shift = shift;
-    ix->boff.assign(H + 1, 0);
+    // Buckets: one per zero-shift hash, in hash order; entries are the
+    // distinct strings (ascending) whose last block hashes there.
+    std::vector<uint32_t> bucket_of(H, 0xffffffffu);
+    uint32_t nb = 0;
     for (uint32_t h = 0; h < H; h++)
-        ix->boff[h + 1] = ix->boff[h] + bcount[h];
-    ix->bu.assign(ix->boff[H], 0);
+        if (shift[h] == 0)
+            bucket_of[h] = nb++;
+    ix->shift16.assign(H, 0);
+    for (uint32_t h = 0; h < H; h++)
+        ix->shift16[h] = shift[h] ? (uint16_t)shift[h] : (uint16_t)(0x8000u | bucket_of[h]);
+    ix->boff.assign(nb + 1, 0);
+    for (uint32_t h = 0; h < H; h++)
+        if (shift[h] == 0)
+            ix->boff[bucket_of[h] + 1] = bcount[h];
+    for (uint32_t b = 0; b < nb; b++)
+        ix->boff[b + 1] += ix->boff[b];
+    // Filter key: codes of the (up to 16) characters just before the last
+    // block, first character in the low bits.
+    const uint32_t kl = std::min<uint32_t>(16, m - B);
+    ix->key_len = kl;
+    ix->bu.assign(ix->du, 0);
+    ix->bkey.assign(ix->du, 0);
     std::vector<uint32_t> fillp(ix->boff.begin(), ix->boff.end() - 1);
-    for (uint32_t u = 0; u < ix->du; u++) {  // ascending ranks per bucket
-        uint32_t h = wm_block_hash(ix->upats.data() + (uint64_t)u * m + m - B, B, best_sh);
-        ix->bu[fillp[h]++] = u;
-    }
-    ix->prefix.assign(ix->du, 0);
-    for (uint32_t u = 0; u < ix->du; u++) {
-        uint32_t key = 0;
-        for (uint32_t k = 0; k < std::min<uint32_t>(m, 4); k++)
-            key |= (uint32_t)ix->upats[(uint64_t)u * m + k] << (8 * k);
-        ix->prefix[u] = key;
+    for (uint32_t u = 0; u < ix->du; u++) {  // ascending ranks within a bucket
+        const uint8_t *p = ix->upats.data() + (uint64_t)u * m;
+        uint32_t h = wm_block_hash(p + m - B, B, best_sh);
+        uint32_t slot = fillp[bucket_of[h]]++;
+        ix->bu[slot] = u;
+        ix->bkey[slot] = kl ? wm_block_hash(p + m - B - kl, kl, best_sh) : 0;
     }
     double sum = 0;
     uint32_t zeros = 0;
-    for (uint8_t s : shift) {
-        sum += s;
-        zeros += s == 0;
+    for (uint8_t sv : shift) {
+        sum += sv;
+        zeros += sv == 0;
     }
     ix->mean_shift = sum / H;
     ix->zero_shift = zeros;
+    ix->n_buckets = nb;
 
+    // Device image: SHIFT (u16) | bucket offsets | keys | ranks, then the
+    // distinct strings and the id CSR. The first four are what the window
+    // loop reads and what LDS placement copies.
     ix->image.clear();
-    ix->off_a = put(ix->image, ix->shift.data(), ix->shift.size());
-    ix->table_bytes = align_up(H, 16);
+    ix->off_a = put(ix->image, ix->shift16.data(), ix->shift16.size());
     ix->off_b = put(ix->image, ix->boff.data(), ix->boff.size());
-    ix->off_c = put(ix->image, ix->bu.data(), std::max<size_t>(ix->bu.size(), 1));
-    ix->off_d = put(ix->image, ix->prefix.data(), ix->prefix.size());
+    ix->off_c = put(ix->image, ix->bkey.data(), ix->bkey.size());
+    ix->off_d = put(ix->image, ix->bu.data(), ix->bu.size());
+    ix->table_bytes = align_up(ix->off_d + 4 * ix->bu.size(), 16);  // contiguous from off_a = 0
     ix->off_e = put(ix->image, ix->upats.data(), ix->upats.size());
     ix->off_f = put(ix->image, ix->uoff.data(), ix->uoff.size());
     ix->off_g = put(ix->image, ix->uids.data(), ix->uids.size());
@@ -646,7 +706,8 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
     try {
         mpm_batch *b = new mpm_batch();
         b->reqs.assign(reqs, reqs + count);
-        std::map<std::tuple<const mpm_index *, uint32_t, uint32_t, uint32_t, uint32_t>, size_t> key;
+        std::map<std::tuple<const mpm_index *, uint32_t, uint32_t, uint32_t, uint32_t, bool>, size_t>
+            key;
         for (uint32_t k = 0; k < count; k++) {
             const mpm_request &r = reqs[k];
             if (!r.idx || !r.d_total || (r.n && !r.d_text) || (r.capacity && !r.d_out)) {
@@ -669,7 +730,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return st;
             }
             auto kk = std::make_tuple(r.idx, cfg.lane_bytes, cfg.block_threads, cfg.placement,
-                                      r.variant.grid);
+                                      r.variant.grid, cfg.swar);
             auto it = key.find(kk);
             size_t gi;
             if (it == key.end()) {

@@ -23,7 +23,7 @@ namespace mpm {
 // s >= first_term, and then u = s - first_term is the string's rank.
 struct AcDev {
     const void *dfa;        // uint16 or uint32 entries
-    const uint8_t *cls;     // 256 entries: column per byte value
+    const uint8_t *cls;     // 256 uint16 entries: byte offset of the column within a row
     const uint32_t *uoff;   // n_unique + 1: CSR offsets into uids
     const uint32_t *uids;   // d: ascending pattern ids per distinct string
     uint32_t n_states;
@@ -32,22 +32,35 @@ struct AcDev {
     uint32_t m;
     uint32_t dfa_bytes;     // bytes of the table (multiple of 16)
     uint32_t dupfree;       // every distinct string has exactly one id
+    // Byte classes without a lookup table, usable when the pattern bytes
+    // have distinct 3-bit codes (b >> swar_shift) & 7: perm_byte selects, per
+    // code, the only byte with that code that is a pattern byte (or a byte
+    // whose code differs, for unused codes); perm_col gives its column's byte
+    // offset (0 for unused codes). Bytes that are not their code's pattern
+    // byte take column 0.
+    uint32_t swar_ok;
+    uint32_t swar_shift;
+    uint32_t perm_byte_lo, perm_byte_hi, perm_col_lo, perm_col_hi;
 };
 
-// Wu-Manber tables. A block of B characters hashes to
-// sum_k ((c_k >> code_shift) & 3) << 2k (first character in the low bits).
+// Wu-Manber tables. Characters map to 2-bit codes (c >> code_shift) & 3; a
+// string of k characters hashes to sum_j code(c_j) << 2j (first character
+// in the low bits). SHIFT is stored per block hash as a uint16: the shift
+// when positive, else 0x8000 | bucket. Bucket b lists, in ascending order,
+// the distinct strings whose last block hashes to that value
+// (bu[boff[b] .. boff[b+1])), each with a filter key: the hash of the
+// key_len characters just before its last block.
 struct WmDev {
-    const uint8_t *shift;   // 4^B entries
-    const uint32_t *boff;   // 4^B + 1 CSR offsets into bu
-    const uint32_t *bu;     // distinct-string ranks whose last block hashes to h, ascending
-    const uint32_t *prefix; // per distinct string: its first min(m, 4) bytes, little-endian
+    const uint8_t *tables;  // shift16 | boff | bkey | bu, contiguous (table_bytes)
+    uint32_t off_boff, off_bkey, off_bu;  // byte offsets inside `tables`
     const uint8_t *pats;    // distinct strings, n_unique * m bytes, ascending
     const uint32_t *uoff;
     const uint32_t *uids;
     uint32_t B;
     uint32_t code_shift;
     uint32_t m;
-    uint32_t shift_bytes;   // 4^B rounded up to 16
+    uint32_t key_len;
+    uint32_t table_bytes;
     uint32_t dupfree;
 };
 
@@ -99,15 +112,18 @@ struct mpm_index {
     uint32_t n_classes = 0;
     uint8_t class_bytes[256] = {0};
     uint8_t cls[256] = {0};
+    uint32_t swar_ok = 0, swar_shift = 0;
+    uint8_t perm_byte[8] = {0}, perm_col[8] = {0};
     uint64_t n_states = 0;
     uint32_t state_bytes = 0;
     std::vector<uint32_t> dfa;          // n_states * (1 + n_classes)
 
     // Wu-Manber
-    uint32_t B = 0, code_shift = 0, zero_shift = 0;
+    uint32_t B = 0, code_shift = 0, zero_shift = 0, n_buckets = 0, key_len = 0;
     double mean_shift = 0;
-    std::vector<uint8_t> shift;
-    std::vector<uint32_t> boff, bu, prefix;
+    std::vector<uint8_t> shift;       // SHIFT per block hash
+    std::vector<uint16_t> shift16;    // SHIFT, or 0x8000 | bucket when zero
+    std::vector<uint32_t> boff, bu, bkey;
 
     // Device image: host copy, offsets, and the caller-owned device buffer.
     std::vector<uint8_t> image;
@@ -127,6 +143,7 @@ struct LaunchCfg {
     uint32_t placement;   // resolved: LDS or GLOBAL
     uint32_t grid;        // resolved workgroup count
     uint32_t lds_bytes;   // dynamic LDS per workgroup
+    bool swar;            // AC: byte classes computed in registers
 };
 mpm_status resolve_variant(const mpm_index *idx, const mpm_variant *v, uint64_t ntiles_hint,
                            LaunchCfg *cfg);

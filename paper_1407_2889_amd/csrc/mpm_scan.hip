@@ -32,11 +32,23 @@
 //        against HASH/PREFIX and the pattern bytes.
 #include <hip/hip_runtime.h>
 
+#include <string.h>
+
 #include <mutex>
 
 #include "mpm_internal.h"
 
 namespace mpm {
+
+// Address-space qualified pointers: LDS tables must be read with ds_read and
+// global data with global_load (a generic pointer would give flat loads).
+#define LDS_AS __attribute__((address_space(3)))
+#define GLB_AS __attribute__((address_space(1)))
+template <typename T> using lds_cptr = const LDS_AS T *;
+template <typename T> using glb_cptr = const GLB_AS T *;
+template <bool InLds, typename T> struct TabPtr { using type = glb_cptr<T>; };
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte load/store unit
+template <typename T> struct TabPtr<true, T> { using type = lds_cptr<T>; };
 
 static const int K_SLOTS = 4;  // occurrences a lane keeps in registers
 static const uint32_t SPIN_LIMIT = 1u << 24;
@@ -44,14 +56,18 @@ static const uint32_t SPIN_LIMIT = 1u << 24;
 // ---------------------------------------------------------------------------
 // Look-back status words
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t ld_acquire(const uint64_t *p)
+// A status word carries its flag and its value together, so no other memory
+// is published through it: relaxed device-coherent atomics suffice. (Acquire
+// or release at device scope would write back or invalidate the L2 of every
+// chunk's XCD, which costs far more than the scan of a chunk.)
+__device__ __forceinline__ uint64_t ld_status(const uint64_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void st_release(uint64_t *p, uint64_t v)
+__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t make_status(uint32_t epoch, uint32_t flag, uint64_t val)
@@ -60,44 +76,66 @@ __device__ __forceinline__ uint64_t make_status(uint32_t epoch, uint32_t flag, u
            (val & ST_VAL_MASK);
 }
 
-// Publish this chunk's count and find the sum of all earlier chunks of the
-// same text. flag 1: count of this chunk only; flag 2: inclusive prefix.
-__device__ uint64_t look_back(uint64_t *status, uint64_t g, uint64_t agg, bool first,
+// Publish this chunk's count and return the sum of all earlier chunks of the
+// same text (decoupled look-back). flag 1: this chunk's count only; flag 2:
+// inclusive prefix. Run by the 64 lanes of wave 0: each probe reads the 64
+// preceding status words at once and stops at the nearest inclusive one.
+// Chunks before the text's first chunk count as an inclusive zero.
+__device__ __forceinline__ uint64_t look_back(uint64_t *status, uint64_t g, uint64_t first_g, uint64_t agg,
                               uint32_t epoch, uint32_t *err)
 {
-    if (first) {
-        st_release(&status[g], make_status(epoch, 2, agg));
+    const int lane = threadIdx.x & 63;
+    if (g == first_g) {
+        if (lane == 0)
+            st_status(&status[g], make_status(epoch, 2, agg));
         return 0;
     }
-    st_release(&status[g], make_status(epoch, 1, agg));
-    uint64_t excl = 0;
-    uint64_t j = g - 1;
-    uint32_t spins = 0;
+    if (lane == 0)
+        st_status(&status[g], make_status(epoch, 1, agg));
     const uint64_t tag = epoch & ST_EPOCH_MASK;
+    uint64_t excl = 0;
+    int64_t top = (int64_t)g - 1;  // status index probed by lane 0
+    uint32_t spins = 0;
     while (true) {
-        uint64_t v = ld_acquire(&status[j]);
-        uint32_t fl = (uint32_t)(v >> ST_VAL_BITS) & 3u;
-        if ((v >> 38) != tag || fl == 0) {
+        const int64_t j = top - lane;
+        uint32_t fl = 2;
+        uint64_t val = 0;
+        if (j >= (int64_t)first_g) {
+            const uint64_t v = ld_status(&status[j]);
+            fl = ((v >> 38) == tag) ? ((uint32_t)(v >> ST_VAL_BITS) & 3u) : 0u;
+            val = v & ST_VAL_MASK;
+        }
+        const uint64_t ready = __ballot(fl != 0);
+        const uint64_t incl = __ballot(fl == 2);
+        const int k = incl ? __ffsll((long long)incl) - 1 : 64;      // nearest inclusive lane
+        const uint64_t need = k >= 63 ? ~0ull : ((2ull << k) - 1);   // lanes 0..k
+        if ((ready & need) != need) {
             if (++spins > SPIN_LIMIT) {  // never expected; keeps every wave finite
-                atomicOr(err, 1u);
+                if (lane == 0)
+                    atomicOr(err, 1u);
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += v & ST_VAL_MASK;
-        if (fl == 2)
+        uint64_t x = lane <= k ? val : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            x += __shfl_xor(x, o, 64);
+        excl += x;
+        if (k < 64)
             break;
-        --j;
+        top -= 64;
     }
-    st_release(&status[g], make_status(epoch, 2, excl + agg));
+    if (lane == 0)
+        st_status(&status[g], make_status(epoch, 2, excl + agg));
     return excl;
 }
 
 // Lane-ordered exclusive offsets within the chunk plus the chunk offset.
 template <int W>
 __device__ __forceinline__ uint64_t chunk_offsets(uint32_t cnt, uint64_t *s_scan, uint64_t *status,
-                                                  uint64_t g, bool first, bool last,
+                                                  uint64_t g, uint64_t first_g, bool last,
                                                   uint64_t *total, uint32_t epoch, uint32_t *err)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -111,38 +149,46 @@ __device__ __forceinline__ uint64_t chunk_offsets(uint32_t cnt, uint64_t *s_scan
     if (lane == 63)
         s_scan[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wave == 0) {
         uint64_t run = 0;
 #pragma unroll
-        for (int w = 0; w < W / 64; ++w) {
-            uint64_t t = s_scan[w];
-            s_scan[w] = run;
-            run += t;
+        for (int w = 0; w < W / 64; ++w)
+            run += s_scan[w];
+        uint64_t excl = look_back(status, g, first_g, run, epoch, err);
+        if (lane == 0) {
+            uint64_t r = 0;
+            for (int w = 0; w < W / 64; ++w) {
+                uint64_t t = s_scan[w];
+                s_scan[w] = r;
+                r += t;
+            }
+            s_scan[W / 64] = excl;
+            if (last)
+                *total = excl + run;
         }
-        uint64_t excl = look_back(status, g, run, first, epoch, err);
-        s_scan[W / 64] = excl;
-        if (last)
-            *total = excl + run;
     }
     __syncthreads();
     return s_scan[W / 64] + s_scan[wave] + (x - cnt);
 }
 
 // Write the ids of distinct string u at position pos, advancing ob.
-__device__ __forceinline__ void write_ids(mpm_match *__restrict__ out, uint64_t cap, uint64_t &ob,
-                                          uint32_t pos, uint32_t u, const uint32_t *__restrict__ uoff,
-                                          const uint32_t *__restrict__ uids, uint32_t dupfree)
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_t &ob, uint32_t pos,
+                                          uint32_t u, const GLB_AS uint32_t *uoff,
+                                          const GLB_AS uint32_t *uids, uint32_t dupfree)
 {
+    GLB_AS v2u *out = (GLB_AS v2u *)out_;
     if (dupfree) {
         if (ob < cap)
-            *(uint2 *)&out[ob] = make_uint2(pos, uids[u]);
+            out[ob] = v2u{pos, uids[u]};
         ++ob;
         return;
     }
     const uint32_t b = uoff[u], e = uoff[u + 1];
     for (uint32_t j = b; j < e; ++j) {
         if (ob < cap)
-            *(uint2 *)&out[ob] = make_uint2(pos, uids[j]);
+            out[ob] = v2u{pos, uids[j]};
         ++ob;
     }
 }
@@ -151,234 +197,309 @@ __device__ __forceinline__ void write_ids(mpm_match *__restrict__ out, uint64_t 
 template <int W>
 __device__ __forceinline__ void copy_to_lds(uint8_t *dst, const uint8_t *src, uint32_t bytes)
 {
-    const uint4 *s = (const uint4 *)src;
-    uint4 *d = (uint4 *)dst;
+    glb_cptr<v4u> s = (glb_cptr<v4u>)src;
+    LDS_AS v4u *d = (LDS_AS v4u *)dst;
     for (uint32_t k = threadIdx.x; k < bytes / 16; k += W)
         d[k] = s[k];
+}
+
+// Stream bytes [p, end) of a text through registers: single bytes up to a
+// 16-byte boundary, then 64-byte blocks (the next block's loads are issued
+// before the current one is consumed), then 16-byte pieces, then bytes.
+// one(byte, pos) and sixteen(v4u, pos) consume in text order.
+template <class F1, class F16>
+__device__ __forceinline__ void stream_text(glb_cptr<uint8_t> text, uint64_t p, uint64_t end,
+                                            F1 &&one, F16 &&sixteen)
+{
+    while (p < end && (((uintptr_t)(text + p)) & 15u)) {
+        one((uint32_t)text[p], p);
+        ++p;
+    }
+    if (p + 64 <= end) {
+        glb_cptr<v4u> q = (glb_cptr<v4u>)(text + p);
+        v4u c0 = q[0], c1 = q[1], c2 = q[2], c3 = q[3];
+        while (true) {
+            const bool more = p + 128 <= end;
+            glb_cptr<v4u> nq = (glb_cptr<v4u>)(text + (more ? p + 64 : p));
+            const v4u n0 = nq[0], n1 = nq[1], n2 = nq[2], n3 = nq[3];
+            sixteen(c0, p);
+            sixteen(c1, p + 16);
+            sixteen(c2, p + 32);
+            sixteen(c3, p + 48);
+            p += 64;
+            if (!more)
+                break;
+            c0 = n0;
+            c1 = n1;
+            c2 = n2;
+            c3 = n3;
+        }
+    }
+    while (p + 16 <= end) {
+        sixteen(*(glb_cptr<v4u>)(text + p), p);
+        p += 16;
+    }
+    while (p < end) {
+        one((uint32_t)text[p], p);
+        ++p;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Aho-Corasick walker
 // ---------------------------------------------------------------------------
-template <typename St, bool LDS>
+// Column byte offsets of four text bytes at once (Swar variant): 3-bit codes
+// pick each byte's expected pattern byte and column through v_perm; a SWAR
+// zero-byte test sends every byte that is not its code's pattern byte to
+// column 0 (the root).
+__device__ __forceinline__ uint32_t swar_cols(uint32_t w, uint32_t sh, uint32_t pb_lo,
+                                              uint32_t pb_hi, uint32_t pc_lo, uint32_t pc_hi)
+{
+    const uint32_t code = (w >> sh) & 0x07070707u;
+    const uint32_t expect = __builtin_amdgcn_perm(pb_hi, pb_lo, code);
+    const uint32_t col = __builtin_amdgcn_perm(pc_hi, pc_lo, code);
+    const uint32_t x = w ^ expect;
+    const uint32_t nz = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;  // bit 7: byte != 0
+    return col & ~((nz >> 7) * 0xFFu);
+}
+
+template <typename St, bool InLds, bool Swar>
 struct AcWalk {
     using Dev = AcDev;
-    const St *dfa;
-    const uint8_t *cls;
-    uint32_t cp, first_term, m;
-
-    static uint32_t lds_bytes(const AcDev &a, uint32_t /*W*/, uint32_t /*L*/)
-    {
-        return 256 + (LDS ? a.dfa_bytes : 0);
-    }
+    typename TabPtr<InLds, uint8_t>::type dfab;  // table, addressed in bytes
+    lds_cptr<uint16_t> cls;                      // column byte offset per byte value
+    uint32_t rowb, first_term, m, sh, pb_lo, pb_hi, pc_lo, pc_hi;
 
     template <int W>
-    __device__ void setup(const AcDev &a, uint8_t *smem, uint32_t /*text_lds_bytes*/)
+    __device__ __forceinline__ void setup(const AcDev &a, uint8_t *smem, uint32_t /*unused*/)
     {
-        cp = a.cp;
+        rowb = a.cp * (uint32_t)sizeof(St);
         first_term = a.first_term;
         m = a.m;
-        copy_to_lds<W>(smem, a.cls, 256);
-        cls = smem;
-        if (LDS) {
-            copy_to_lds<W>(smem + 256, (const uint8_t *)a.dfa, a.dfa_bytes);
-            dfa = (const St *)(smem + 256);
+        sh = a.swar_shift;
+        pb_lo = a.perm_byte_lo;
+        pb_hi = a.perm_byte_hi;
+        pc_lo = a.perm_col_lo;
+        pc_hi = a.perm_col_hi;
+        copy_to_lds<W>(smem, a.cls, 512);
+        cls = (lds_cptr<uint16_t>)smem;
+        if (InLds) {
+            copy_to_lds<W>(smem + 512, (const uint8_t *)a.dfa, a.dfa_bytes);
+            dfab = (typename TabPtr<InLds, uint8_t>::type)(smem + 512);
         } else {
-            dfa = (const St *)a.dfa;
+            dfab = (typename TabPtr<InLds, uint8_t>::type)a.dfa;
         }
         __syncthreads();
     }
 
-    template <int W>
-    __device__ void begin_chunk(const TextDesc &, uint64_t, uint64_t) {}
-
-    template <class F>
-    __device__ __forceinline__ void chunk16(uint32_t &s, const uint4 c, uint64_t p, F &cb) const
+    // One transition: row s, column at byte offset coloff.
+    __device__ __forceinline__ uint32_t next(uint32_t s, uint32_t coloff) const
     {
-        uint32_t st[16];
-        uint32_t mx = 0;
-        const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            uint32_t b = (w[k >> 2] >> (8 * (k & 3))) & 0xffu;
-            s = dfa[s * cp + cls[b]];
-            st[k] = s;
-            mx = max(mx, s);
-        }
-        if (mx >= first_term) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (st[k] >= first_term)
-                    cb(p + k + 1 - m, st[k] - first_term);
-        }
+        const uint32_t off = sizeof(St) == 2 ? __umul24(s, rowb) + coloff : s * rowb + coloff;
+        return *(typename TabPtr<InLds, St>::type)(dfab + off);
     }
 
-    // Walk bytes [p, end) of the text from the root; cb(start, u) for every
-    // terminal state reached (start = index of the byte - m + 1).
+    // Walk bytes [p, end) from the root; cb(start, u) for every terminal
+    // state reached (start = index of the byte - m + 1).
     template <class F>
-    __device__ __forceinline__ void walk(const uint8_t *__restrict__ text, uint64_t p, uint64_t end,
-                                         F &&cb) const
+    __device__ __forceinline__ void walk(glb_cptr<uint8_t> text, uint64_t p, uint64_t end,
+                                         F &cb) const
     {
         uint32_t s = 0;
-        while (p < end && (((uintptr_t)(text + p)) & 15u)) {
-            s = dfa[s * cp + cls[text[p]]];
-            if (s >= first_term)
-                cb(p + 1 - m, s - first_term);
-            ++p;
-        }
-        if (p + 64 <= end) {
-            const uint4 *q = (const uint4 *)(text + p);
-            uint4 c0 = q[0], c1 = q[1], c2 = q[2], c3 = q[3];
-            while (true) {
-                const bool more = p + 128 <= end;
-                const uint4 *nq = (const uint4 *)(text + (more ? p + 64 : p));
-                uint4 n0 = nq[0], n1 = nq[1], n2 = nq[2], n3 = nq[3];
-                chunk16(s, c0, p, cb);
-                chunk16(s, c1, p + 16, cb);
-                chunk16(s, c2, p + 32, cb);
-                chunk16(s, c3, p + 48, cb);
-                p += 64;
-                if (!more)
-                    break;
-                c0 = n0;
-                c1 = n1;
-                c2 = n2;
-                c3 = n3;
-            }
-        }
-        while (p + 16 <= end) {
-            uint4 c = *(const uint4 *)(text + p);
-            chunk16(s, c, p, cb);
-            p += 16;
-        }
-        while (p < end) {
-            s = dfa[s * cp + cls[text[p]]];
-            if (s >= first_term)
-                cb(p + 1 - m, s - first_term);
-            ++p;
-        }
+        stream_text(
+            text, p, end,
+            [&](uint32_t b, uint64_t q) {
+                s = next(s, cls[b]);
+                if (s >= first_term)
+                    cb(q + 1 - m, s - first_term);
+            },
+            [&](const v4u c, uint64_t q) {
+                uint32_t cw[4];
+                if (Swar) {
+                    cw[0] = swar_cols(c.x, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                    cw[1] = swar_cols(c.y, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                    cw[2] = swar_cols(c.z, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                    cw[3] = swar_cols(c.w, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                }
+                uint32_t st[16];
+                uint32_t mx = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    uint32_t col;
+                    if (Swar) {
+                        col = (cw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                    } else {
+                        const uint32_t w = k < 4 ? c.x : k < 8 ? c.y : k < 12 ? c.z : c.w;
+                        col = cls[(w >> (8 * (k & 3))) & 0xffu];
+                    }
+                    s = next(s, col);
+                    st[k] = s;
+                    mx = max(mx, s);
+                }
+                if (mx >= first_term) {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (st[k] >= first_term)
+                            cb(q + k + 1 - m, st[k] - first_term);
+                }
+            });
     }
 
     // Lane range: starts [lo, hi) relative to the chunk at text offset base.
     template <class F>
-    __device__ __forceinline__ void lane(const TextDesc &td, uint64_t base, uint32_t lo, uint32_t hi,
-                                         F &&cb) const
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
     {
-        uint64_t p = base + lo;
         uint64_t end = base + hi + m - 1;
-        if (end > td.n)
-            end = td.n;
-        walk(td.text, p, end, cb);
+        if (end > n)
+            end = n;
+        walk(text, base + lo, end, cb);
     }
 };
 
 // ---------------------------------------------------------------------------
 // Wu-Manber walker
 // ---------------------------------------------------------------------------
-template <bool LDS>
+static const int WM_QUEUE = 4;  // filtered candidates kept before exact checks
+
+// 2-bit codes of four bytes, first byte in the low bits.
+__device__ __forceinline__ uint32_t codes4(uint32_t w, uint32_t sh)
+{
+    uint32_t x = (w >> sh) & 0x03030303u;
+    x = (x | (x >> 6)) & 0x000F000Fu;
+    return (x | (x >> 12)) & 0xFFu;
+}
+
+template <bool InLds>
 struct WmWalk {
     using Dev = WmDev;
-    const uint8_t *shift;
-    uint8_t *tb;  // chunk text in LDS
-    const uint32_t *boff, *bu, *prefix;
-    const uint8_t *pats;
-    uint32_t m, B, sh;
+    typename TabPtr<InLds, uint16_t>::type sh16;
+    typename TabPtr<InLds, uint32_t>::type boff, bkey, bu;
+    glb_cptr<uint8_t> pats;
+    uint32_t m, B, csh, kl, hmask, kmask;
 
-    static uint32_t lds_bytes(const WmDev &a, uint32_t W, uint32_t L)
-    {
-        uint32_t text = (W * L + 64 + 15) & ~15u;
-        return text + (LDS ? a.shift_bytes : 0);
-    }
-
-    // LDS: the chunk's text first, then SHIFT when it is placed in LDS.
     template <int W>
-    __device__ void setup(const WmDev &a, uint8_t *smem, uint32_t text_bytes)
+    __device__ __forceinline__ void setup(const WmDev &a, uint8_t *smem, uint32_t /*unused*/)
     {
         m = a.m;
         B = a.B;
-        sh = a.code_shift;
-        boff = a.boff;
-        bu = a.bu;
-        prefix = a.prefix;
-        pats = a.pats;
-        tb = smem;
-        shift = a.shift;
-        if (LDS) {
-            copy_to_lds<W>(smem + text_bytes, a.shift, a.shift_bytes);
-            shift = smem + text_bytes;
+        csh = a.code_shift;
+        kl = a.key_len;
+        hmask = (1u << (2 * B)) - 1u;
+        kmask = kl >= 16 ? 0xffffffffu : ((1u << (2 * kl)) - 1u);
+        const uint8_t *base = a.tables;
+        if (InLds) {
+            copy_to_lds<W>(smem, a.tables, a.table_bytes);
+            base = smem;
         }
+        sh16 = (typename TabPtr<InLds, uint16_t>::type)base;
+        boff = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_boff);
+        bkey = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bkey);
+        bu = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bu);
+        pats = (glb_cptr<uint8_t>)a.pats;
         __syncthreads();
     }
 
-    // Stage the chunk's bytes [base, base + starts + m - 1) into LDS.
-    template <int W>
-    __device__ void begin_chunk(const TextDesc &td, uint64_t base, uint64_t starts)
+    // 32 bits of the 96-bit history {h2:h1:h0} from bit o (o <= 64).
+    __device__ __forceinline__ static uint32_t bits(uint32_t h0, uint32_t h1, uint32_t h2, uint32_t o)
     {
-        uint64_t len = starts + m - 1;
-        if (base + len > td.n)
-            len = td.n - base;
-        const uint8_t *src = td.text + base;
-        const uint32_t L32 = (uint32_t)len;
-        if ((((uintptr_t)src) & 15u) == 0) {
-            const uint32_t nv = L32 / 16;
-            for (uint32_t k = threadIdx.x; k < nv; k += W)
-                ((uint4 *)tb)[k] = ((const uint4 *)src)[k];
-            for (uint32_t k = nv * 16 + threadIdx.x; k < L32; k += W)
-                tb[k] = src[k];
-        } else {
-            for (uint32_t k = threadIdx.x; k < L32; k += W)
-                tb[k] = src[k];
-        }
-        __syncthreads();
+        const uint32_t q = o >> 5;
+        const uint32_t lo = q == 0 ? h0 : (q == 1 ? h1 : h2);
+        const uint32_t hi = q == 0 ? h1 : h2;
+        return __builtin_amdgcn_alignbit(hi, lo, o & 31u);
     }
 
+    // Window loop (Algorithm 5) over one lane's range, the text streamed
+    // through registers. The history keeps the 2-bit codes of the last 48
+    // characters read (positions [e-48, e), position q at bit 2(q-e+48)).
+    // Every window end nx < e is examined: the hash of its last B
+    // characters picks SHIFT; a zero shift sends the window to its bucket,
+    // where the filter key (codes of the key_len characters before the block)
+    // must equal the candidate's before the window is compared byte by byte
+    // with the pattern.
     template <class F>
-    __device__ __forceinline__ void verify(uint32_t i, uint32_t h, uint64_t base, F &cb) const
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
     {
-        const uint32_t ws = i + 1 - m;
-        const uint32_t pk = m < 4 ? m : 4;
-        uint32_t key = 0;
-        for (uint32_t k = 0; k < pk; ++k)
-            key |= (uint32_t)tb[ws + k] << (8 * k);
-        const uint32_t e = boff[h + 1];
-        for (uint32_t j = boff[h]; j < e; ++j) {
-            const uint32_t u = bu[j];
-            if (prefix[u] != key)
-                continue;
-            const uint8_t *pp = pats + (uint64_t)u * m;
-            bool ok = true;
-            for (uint32_t k = pk; k < m; ++k)
-                if (pp[k] != tb[ws + k]) {
-                    ok = false;
-                    break;
-                }
-            if (ok) {  // distinct strings of equal length: at most one matches
-                cb(base + ws, u);
-                break;
-            }
-        }
-    }
-
-    template <class F>
-    __device__ __forceinline__ void lane(const TextDesc &, uint64_t base, uint32_t lo, uint32_t hi,
-                                         F &&cb) const
-    {
-        uint32_t i = lo + m - 1;
-        const uint32_t iend = hi + m - 1;
-        while (i < iend) {
-            uint32_t h = 0;
+        const uint64_t p = base + lo;
+        uint64_t end = base + hi + m - 1;
+        if (end > n)
+            end = n;
+        uint64_t nx = p + m - 1;
+        uint64_t e = p;
+        uint32_t h0 = 0, h1 = 0, h2 = 0;
+        uint32_t qn = 0;
+        uint64_t qp[WM_QUEUE];
+        uint32_t qu[WM_QUEUE];
 #pragma unroll
-            for (uint32_t k = 0; k < 8; ++k)
-                if (k < B)
-                    h |= (((uint32_t)tb[i + 1 - B + k] >> sh) & 3u) << (2 * k);
-            const uint32_t s = shift[h];
-            if (s == 0) {
-                verify(i, h, base, cb);
-                i += 1;
-            } else {
-                i += s;
-            }
+        for (int k = 0; k < WM_QUEUE; ++k) {
+            qp[k] = 0;
+            qu[k] = 0;
         }
+        auto flush = [&]() {
+#pragma unroll
+            for (int k = 0; k < WM_QUEUE; ++k) {
+                if ((uint32_t)k < qn) {
+                    const uint64_t st = qp[k] + 1 - m;
+                    glb_cptr<uint8_t> pp = pats + (uint64_t)qu[k] * m;
+                    bool ok = true;
+                    for (uint32_t j = 0; j < m; ++j)
+                        if (pp[j] != text[st + j]) {
+                            ok = false;
+                            break;
+                        }
+                    if (ok)
+                        cb(st, qu[k]);
+                }
+            }
+            qn = 0;
+        };
+        auto windows = [&]() {
+            while (nx < e) {
+                const uint32_t o = 2u * (uint32_t)(nx + 49 - e - B);
+                const uint32_t h = bits(h0, h1, h2, o) & hmask;
+                const uint32_t sv = sh16[h];
+                if (sv & 0x8000u) {
+                    const uint32_t b = sv & 0x7fffu;
+                    const uint32_t key = kl ? (bits(h0, h1, h2, o - 2u * kl) & kmask) : 0u;
+                    const uint32_t je = boff[b + 1];
+                    for (uint32_t j = boff[b]; j < je; ++j) {
+                        if (bkey[j] == key) {
+                            if (qn == (uint32_t)WM_QUEUE)
+                                flush();
+#pragma unroll
+                            for (int k = 0; k < WM_QUEUE; ++k)
+                                if (qn == (uint32_t)k) {
+                                    qp[k] = nx;
+                                    qu[k] = bu[j];
+                                }
+                            ++qn;
+                        }
+                    }
+                    nx += 1;
+                } else {
+                    nx += sv;
+                }
+            }
+        };
+        stream_text(
+            text, p, end,
+            [&](uint32_t b, uint64_t) {
+                h0 = (h0 >> 2) | (h1 << 30);
+                h1 = (h1 >> 2) | (h2 << 30);
+                h2 = (h2 >> 2) | (((b >> csh) & 3u) << 30);
+                e += 1;
+                windows();
+            },
+            [&](const v4u c, uint64_t) {
+                h0 = h1;
+                h1 = h2;
+                h2 = codes4(c.x, csh) | (codes4(c.y, csh) << 8) | (codes4(c.z, csh) << 16) |
+                     (codes4(c.w, csh) << 24);
+                e += 16;
+                windows();
+            });
+        flush();
     }
 };
 
@@ -386,27 +507,9 @@ struct WmWalk {
 // Persistent chunk driver
 // ---------------------------------------------------------------------------
 template <class Walk, int W>
-__device__ __forceinline__ void find_text(const ScanDev &sd, uint64_t g, TextDesc &td)
-{
-    if (sd.ntexts == 1) {
-        td = sd.single;
-        return;
-    }
-    uint32_t lo = 0, hi = sd.ntexts;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (sd.multi[mid].tile_begin <= g)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    td = sd.multi[lo];
-}
-
-template <class Walk, int W>
 __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev sd,
-                                                 const uint32_t *uoff, const uint32_t *uids,
-                                                 uint32_t dupfree, uint32_t text_lds_bytes)
+                                                 const uint32_t *uoff_, const uint32_t *uids_,
+                                                 uint32_t dupfree, uint32_t unused)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ TextDesc s_td;
@@ -414,34 +517,60 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     __shared__ uint32_t s_epoch;
     __shared__ uint64_t s_scan[W / 64 + 1];
 
-    Walk wk;
-    wk.template setup<W>(a, smem, text_lds_bytes);
-    if (threadIdx.x == 0)
-        s_epoch = __hip_atomic_load(&sd.hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-
+    // Launch constants as plain values (no by-reference use of the argument
+    // structs, which would place them in private memory).
+    const uint32_t ntexts = sd.ntexts;
+    const uint64_t ntiles = sd.ntiles;
     const uint32_t L = sd.lane_bytes;
-    const uint64_t chunk = (uint64_t)W * L;
+    uint32_t *const hdr = sd.hdr;
+    uint64_t *const status = sd.status;
+    const TextDesc *const multi = sd.multi;
+    glb_cptr<uint32_t> uoff = (glb_cptr<uint32_t>)uoff_;
+    glb_cptr<uint32_t> uids = (glb_cptr<uint32_t>)uids_;
     const uint32_t m = a.m;
+    const uint64_t chunk = (uint64_t)W * L;
+
+    Walk wk;
+    wk.template setup<W>(a, smem, unused);
+    if (threadIdx.x == 0)
+        s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     while (true) {
         if (threadIdx.x == 0) {
-            uint64_t t = atomicAdd(&sd.hdr[WS_TICKET], 1u);
+            const uint64_t t = atomicAdd(&hdr[WS_TICKET], 1u);
             s_tile = t;
-            if (t < sd.ntiles)
-                find_text<Walk, W>(sd, t, s_td);
+            if (t < ntiles) {
+                if (ntexts == 1) {
+                    s_td = sd.single;
+                } else {  // the text whose chunk range holds t
+                    uint32_t lo = 0, hi = ntexts;
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (multi[mid].tile_begin <= t)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    s_td = multi[lo];
+                }
+            }
         }
         __syncthreads();
         const uint64_t g = s_tile;
-        if (g >= sd.ntiles)
+        if (g >= ntiles)
             break;
-        const TextDesc td = s_td;
+        glb_cptr<uint8_t> text = (glb_cptr<uint8_t>)s_td.text;
+        const uint64_t n = s_td.n;
+        mpm_match *const out = s_td.out;
+        const uint64_t cap = s_td.cap;
+        uint64_t *const total = s_td.total;
+        const uint64_t first_g = s_td.tile_begin;
+        const uint64_t nt = s_td.ntiles;
         const uint32_t epoch = s_epoch;
-        const uint64_t lt = g - td.tile_begin;
-        const uint64_t ns = td.n - m + 1;
+        const uint64_t lt = g - first_g;
+        const uint64_t ns = n - m + 1;
         const uint64_t base = lt * chunk;
         const uint64_t starts = (ns - base) < chunk ? (ns - base) : chunk;
-
-        wk.template begin_chunk<W>(td, base, starts);
 
         const uint32_t lo0 = threadIdx.x * L;
         const uint32_t lo = lo0 < starts ? lo0 : (uint32_t)starts;
@@ -456,7 +585,7 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
             su[k] = 0;
         }
         if (lo < hi) {
-            wk.lane(td, base, lo, hi, [&](uint64_t start, uint32_t u) {
+            wk.lane(text, n, base, lo, hi, [&](uint64_t start, uint32_t u) {
 #pragma unroll
                 for (int k = 0; k < K_SLOTS; ++k)
                     if (nu == (uint32_t)k) {
@@ -469,10 +598,9 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
         }
 
         // Phase B: offsets.
-        const bool first = lt == 0;
-        const bool last = lt + 1 == td.ntiles;
-        uint64_t ob = chunk_offsets<W>(nid, s_scan, sd.status, g, first, last, td.total, epoch,
-                                       &sd.hdr[WS_ERR]);
+        const bool last = lt + 1 == nt;
+        uint64_t ob = chunk_offsets<W>(nid, s_scan, status, g, first_g, last, total, epoch,
+                                       &hdr[WS_ERR]);
 
         // Phase C: ordered writes.
         if (nu != 0) {
@@ -480,10 +608,10 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
 #pragma unroll
                 for (int k = 0; k < K_SLOTS; ++k)
                     if ((uint32_t)k < nu)
-                        write_ids(td.out, td.cap, ob, so[k], su[k], uoff, uids, dupfree);
+                        write_ids(out, cap, ob, so[k], su[k], uoff, uids, dupfree);
             } else {
-                wk.lane(td, base, lo, hi, [&](uint64_t start, uint32_t u) {
-                    write_ids(td.out, td.cap, ob, (uint32_t)start, u, uoff, uids, dupfree);
+                wk.lane(text, n, base, lo, hi, [&](uint64_t start, uint32_t u) {
+                    write_ids(out, cap, ob, (uint32_t)start, u, uoff, uids, dupfree);
                 });
             }
         }
@@ -491,11 +619,11 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     }
 
     if (threadIdx.x == 0) {
-        uint32_t dn = atomicAdd(&sd.hdr[WS_DONE], 1u);
+        const uint32_t dn = atomicAdd(&hdr[WS_DONE], 1u);
         if (dn == gridDim.x - 1) {
-            __hip_atomic_store(&sd.hdr[WS_TICKET], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sd.hdr[WS_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sd.hdr[WS_EPOCH], s_epoch + 1u, __ATOMIC_RELEASE,
+            __hip_atomic_store(&hdr[WS_TICKET], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&hdr[WS_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&hdr[WS_EPOCH], s_epoch + 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -558,23 +686,35 @@ static AcDev ac_dev(const mpm_index *ix)
     a.m = ix->m;
     a.dfa_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
+    a.swar_ok = ix->swar_ok;
+    a.swar_shift = ix->swar_shift;
+    uint32_t w[4];
+    memcpy(&w[0], ix->perm_byte, 4);
+    memcpy(&w[1], ix->perm_byte + 4, 4);
+    memcpy(&w[2], ix->perm_col, 4);
+    memcpy(&w[3], ix->perm_col + 4, 4);
+    a.perm_byte_lo = w[0];
+    a.perm_byte_hi = w[1];
+    a.perm_col_lo = w[2];
+    a.perm_col_hi = w[3];
     return a;
 }
 
 static WmDev wm_dev(const mpm_index *ix)
 {
     WmDev a;
-    a.shift = ix->d_image + ix->off_a;
-    a.boff = (const uint32_t *)(ix->d_image + ix->off_b);
-    a.bu = (const uint32_t *)(ix->d_image + ix->off_c);
-    a.prefix = (const uint32_t *)(ix->d_image + ix->off_d);
+    a.tables = ix->d_image + ix->off_a;
+    a.off_boff = (uint32_t)(ix->off_b - ix->off_a);
+    a.off_bkey = (uint32_t)(ix->off_c - ix->off_a);
+    a.off_bu = (uint32_t)(ix->off_d - ix->off_a);
     a.pats = ix->d_image + ix->off_e;
     a.uoff = (const uint32_t *)(ix->d_image + ix->off_f);
     a.uids = (const uint32_t *)(ix->d_image + ix->off_g);
     a.B = ix->B;
     a.code_shift = ix->code_shift;
     a.m = ix->m;
-    a.shift_bytes = (uint32_t)ix->table_bytes;
+    a.key_len = ix->key_len;
+    a.table_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
     return a;
 }
@@ -595,20 +735,21 @@ static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
 {
     const bool lds = c.placement == MPM_PLACE_LDS;
     if (ix->algo == MPM_ALGO_AC) {
-        if (ix->state_bytes == 2)
-            return lds ? pick_w<AcWalk<uint16_t, true>>(c.block_threads)
-                       : pick_w<AcWalk<uint16_t, false>>(c.block_threads);
-        return lds ? pick_w<AcWalk<uint32_t, true>>(c.block_threads)
-                   : pick_w<AcWalk<uint32_t, false>>(c.block_threads);
+        const bool sw = c.swar;
+        if (ix->state_bytes == 2) {
+            if (lds)
+                return sw ? pick_w<AcWalk<uint16_t, true, true>>(c.block_threads)
+                          : pick_w<AcWalk<uint16_t, true, false>>(c.block_threads);
+            return sw ? pick_w<AcWalk<uint16_t, false, true>>(c.block_threads)
+                      : pick_w<AcWalk<uint16_t, false, false>>(c.block_threads);
+        }
+        if (lds)
+            return sw ? pick_w<AcWalk<uint32_t, true, true>>(c.block_threads)
+                      : pick_w<AcWalk<uint32_t, true, false>>(c.block_threads);
+        return sw ? pick_w<AcWalk<uint32_t, false, true>>(c.block_threads)
+                  : pick_w<AcWalk<uint32_t, false, false>>(c.block_threads);
     }
     return lds ? pick_w<WmWalk<true>>(c.block_threads) : pick_w<WmWalk<false>>(c.block_threads);
-}
-
-static uint32_t text_lds(const mpm_index *ix, uint32_t W, uint32_t L)
-{
-    if (ix->algo != MPM_ALGO_WM)
-        return 0;
-    return (W * L + 64 + 15) & ~15u;
 }
 
 static const uint32_t STATIC_LDS_RESERVE = 512;
@@ -618,7 +759,7 @@ uint64_t tile_bytes(const LaunchCfg &cfg) { return (uint64_t)cfg.lane_bytes * cf
 mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t ntiles,
                            LaunchCfg *cfg)
 {
-    mpm_variant d = {0, 0, 0, 0};
+    mpm_variant d = {0, 0, 0, 0, 0};
     if (v)
         d = *v;
     uint32_t L = d.lane_bytes ? d.lane_bytes : 64;
@@ -630,11 +771,9 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     if (d.placement > MPM_PLACE_GLOBAL)
         return fail(MPM_EINVAL, "variant: unknown placement %u", d.placement);
     const DeviceLimits lim = limits();
-    const uint32_t tl = text_lds(ix, W, L);
-    if (tl + STATIC_LDS_RESERVE + 256 > (uint32_t)lim.max_lds)
-        return fail(MPM_EINVAL, "variant: chunk of %u bytes does not fit in LDS", W * L);
-    const uint64_t table_lds = (ix->algo == MPM_ALGO_AC ? 256 : 0) + ix->table_bytes;
-    const bool fits = tl + table_lds + STATIC_LDS_RESERVE <= (uint64_t)lim.max_lds;
+    const uint32_t fixed = ix->algo == MPM_ALGO_AC ? 512u : 0u;  // AC byte-class map
+    const uint64_t table_lds = fixed + ix->table_bytes;
+    const bool fits = table_lds + STATIC_LDS_RESERVE <= (uint64_t)lim.max_lds;
     uint32_t place = d.placement;
     if (place == MPM_PLACE_AUTO)
         place = fits ? MPM_PLACE_LDS : MPM_PLACE_GLOBAL;
@@ -644,8 +783,8 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     cfg->lane_bytes = L;
     cfg->block_threads = W;
     cfg->placement = place;
-    cfg->lds_bytes = (ix->algo == MPM_ALGO_AC ? 256u : tl) +
-                     (place == MPM_PLACE_LDS ? (uint32_t)ix->table_bytes : 0u);
+    cfg->swar = ix->algo == MPM_ALGO_AC && ix->swar_ok && !(d.flags & MPM_VARIANT_NO_SWAR);
+    cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS ? (uint32_t)ix->table_bytes : 0u);
     cfg->grid = 0;
     if (ntiles) {
         const void *k = kernel_for(ix, *cfg);
@@ -700,17 +839,19 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
                             (int)c.lds_bytes);
     if (ix->algo == MPM_ALGO_AC) {
         AcDev a = ac_dev(ix);
+        const bool sw = c.swar;
+#define MPM_AC(ST, LD, SW) launch_w<AcWalk<ST, LD, SW>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
         if (ix->state_bytes == 2)
-            e = lds ? launch_w<AcWalk<uint16_t, true>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
-                    : launch_w<AcWalk<uint16_t, false>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s);
+            e = lds ? (sw ? MPM_AC(uint16_t, true, true) : MPM_AC(uint16_t, true, false))
+                    : (sw ? MPM_AC(uint16_t, false, true) : MPM_AC(uint16_t, false, false));
         else
-            e = lds ? launch_w<AcWalk<uint32_t, true>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
-                    : launch_w<AcWalk<uint32_t, false>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s);
+            e = lds ? (sw ? MPM_AC(uint32_t, true, true) : MPM_AC(uint32_t, true, false))
+                    : (sw ? MPM_AC(uint32_t, false, true) : MPM_AC(uint32_t, false, false));
+#undef MPM_AC
     } else {
         WmDev a = wm_dev(ix);
-        uint32_t tl = text_lds(ix, c.block_threads, c.lane_bytes);
-        e = lds ? launch_w<WmWalk<true>>(a, c, sd, a.uoff, a.uids, a.dupfree, tl, s)
-                : launch_w<WmWalk<false>>(a, c, sd, a.uoff, a.uids, a.dupfree, tl, s);
+        e = lds ? launch_w<WmWalk<true>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
+                : launch_w<WmWalk<false>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s);
     }
     if (e != hipSuccess)
         return fail(MPM_EHIP, "scan launch: %s", hipGetErrorString(e));

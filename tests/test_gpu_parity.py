@@ -66,11 +66,6 @@ def test_small_workload_all_variants(mpm, small, algo):
     text, P, want = small
     ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
     for v in VARIANTS:
-        if algo == "wm" and v["lane_bytes"] * v["block_threads"] > 128 * 1024:
-            # the chunk's text is staged in LDS: such chunks are rejected
-            with pytest.raises(mpm.MpmError):
-                mpm.workspace_bytes(ix, len(text), mpm.variant(**v))
-            continue
         say(f"[small 1MiB d=100 m=8] {algo} {v}")
         got = gpu_pairs(mpm, ix, text, mpm.variant(**v))
         assert_same(got, want, f"{algo} {v}")
