@@ -120,6 +120,22 @@ def main():
     log(f"[bench] matches={M}")
 
     stream = torch.cuda.current_stream()
+    # Streaming-read ceiling of this device: a coalesced read of a 1 GiB buffer.
+    probe = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    probe.fill_(1)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for _ in range(2):
+        mpm.read_probe(probe, sink)
+    pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in pe:
+        a.record(stream)
+        mpm.read_probe(probe, sink)
+        b.record(stream)
+    torch.cuda.synchronize()
+    probe_ms = float(np.median([a.elapsed_time(b) for a, b in pe]))
+    read_ceiling = probe.numel() / (probe_ms * 1e-3) / 1e9
+    del probe
+
     for _ in range(args.warmup):
         for k in ("ac", "wm"):
             scanners[k].scan_async(dev_text)
@@ -167,6 +183,8 @@ def main():
         "ac_roofline_frac": round((n + 8 * M + ix["ac"].info()["table_bytes"]) / (kms["ac"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "wm_roofline_frac": round((n + 8 * M + ix["wm"].info()["table_bytes"]) / (kms["wm"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "index_build_s": round(build_s, 3),
+        "hbm_read_ceiling_gbs": round(read_ceiling, 1),
+        "frac_of_read_ceiling": {k: round(gbs[k] / read_ceiling, 4) for k in ("ac", "wm")},
         "roofline": {"bound": "hbm", "kernel": f"scan_kernel ({dom.upper()})",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

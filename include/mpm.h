@@ -92,6 +92,10 @@ typedef struct {
  * the pattern bytes have distinct 3-bit codes; this flag forces the byte ->
  * column lookup table in LDS instead. */
 #define MPM_VARIANT_NO_SWAR 1u
+/* Aho-Corasick: each thread walks two lane ranges of its chunk in lockstep
+ * (two independent table-lookup chains); a chunk then holds
+ * 2 * lane_bytes * block_threads starting positions. */
+#define MPM_VARIANT_ILP2 2u
 
 /* Facts about a built index. */
 typedef struct {
@@ -252,6 +256,19 @@ mpm_status mpm_export_wm_shift(const mpm_index *idx, uint8_t *shift);
  * entries) so that ids[uoff[u] .. uoff[u+1]) are the ascending pattern ids of
  * the u-th smallest distinct pattern string. Errors: EINVAL. */
 mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids);
+
+/* ---------------------------------------------------------------------- */
+/* Measurement                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Read `bytes` of device memory d_buf (16-byte aligned) once with coalesced
+ * 16-byte loads (enqueued on `stream`, no wait). Not part of the matching
+ * method: it measures the streaming-read ceiling of the device against which
+ * the scans' text throughput is compared, and gives hardware counters a
+ * kernel of known traffic. d_sink: device uint32, written only in the
+ * (practically impossible) event that the folded data equals a fixed
+ * sentinel. Errors: EINVAL, EHIP. */
+mpm_status mpm_read_probe(const uint8_t *d_buf, uint64_t bytes, uint32_t *d_sink, void *stream);
 
 /* Last error message of this thread ("" if none). */
 const char *mpm_last_error(void);

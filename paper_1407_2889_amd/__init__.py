@@ -50,6 +50,7 @@ class Opts(C.Structure):
 
 
 VARIANT_NO_SWAR = 1
+VARIANT_ILP2 = 2
 
 
 class Variant(C.Structure):
@@ -116,6 +117,7 @@ _sig("mpm_batch_free", None, [_vp])
 _sig("mpm_export_ac", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_export_wm_shift", C.c_int32, [_vp, _vp])
 _sig("mpm_export_unique", C.c_int32, [_vp, _vp, _vp])
+_sig("mpm_read_probe", C.c_int32, [_vp, _u64, _vp, _vp])
 
 # Every symbol include/mpm.h declares (checked by the CPU tests).
 EXPORTS = [
@@ -123,7 +125,7 @@ EXPORTS = [
     "mpm_index_info", "mpm_workspace_bytes", "mpm_scan", "mpm_scan_sync", "mpm_batch_plan",
     "mpm_batch_device_bytes", "mpm_batch_upload", "mpm_batch_run", "mpm_batch_capture",
     "mpm_batch_replay", "mpm_batch_groups", "mpm_batch_free", "mpm_export_ac",
-    "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version",
+    "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
 ]
 
 
@@ -330,6 +332,12 @@ def scan(ix: Index, text, capacity: int | None = None, var: Variant | None = Non
         _check(st, "mpm_scan_sync")
         return out[: tot.value]
     raise MpmError(MPM_EOVERFLOW, "scan")
+
+
+def read_probe(buf, sink, stream=None):
+    """Stream-read a 16-byte aligned CUDA tensor once (HBM ceiling probe)."""
+    _check(_L.mpm_read_probe(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                             C.c_void_p(sink.data_ptr()), _stream_handle(stream)), "mpm_read_probe")
 
 
 def pairs_numpy(t) -> tuple[np.ndarray, np.ndarray]:

@@ -706,7 +706,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
     try {
         mpm_batch *b = new mpm_batch();
         b->reqs.assign(reqs, reqs + count);
-        std::map<std::tuple<const mpm_index *, uint32_t, uint32_t, uint32_t, uint32_t, bool>, size_t>
+        std::map<std::tuple<const mpm_index *, uint32_t, uint32_t, uint32_t, uint32_t, int>, size_t>
             key;
         for (uint32_t k = 0; k < count; k++) {
             const mpm_request &r = reqs[k];
@@ -730,7 +730,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return st;
             }
             auto kk = std::make_tuple(r.idx, cfg.lane_bytes, cfg.block_threads, cfg.placement,
-                                      r.variant.grid, cfg.swar);
+                                      r.variant.grid, cfg.swar * 2 + (cfg.ilp == 2));
             auto it = key.find(kk);
             size_t gi;
             if (it == key.end()) {

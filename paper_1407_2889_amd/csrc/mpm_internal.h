@@ -144,6 +144,7 @@ struct LaunchCfg {
     uint32_t grid;        // resolved workgroup count
     uint32_t lds_bytes;   // dynamic LDS per workgroup
     bool swar;            // AC: byte classes computed in registers
+    uint32_t ilp;         // virtual lanes per thread (1 or 2)
 };
 mpm_status resolve_variant(const mpm_index *idx, const mpm_variant *v, uint64_t ntiles_hint,
                            LaunchCfg *cfg);

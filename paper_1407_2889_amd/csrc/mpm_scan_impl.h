@@ -1,0 +1,846 @@
+// Scan kernels for gfx950 (CDNA4, wave64).
+//
+// Decomposition (the paper's data-parallel strategy, Section 4.2.1, recast
+// for CDNA): the starting positions of a text are cut into chunks of
+// block_threads * lane_bytes positions. A persistent grid of workgroups takes
+// chunks in ascending order from an atomic ticket counter. Inside a chunk,
+// lane k owns lane_bytes consecutive starting positions and reads m - 1 bytes
+// beyond them (the overlap of Section 4.2.1), so every occurrence is found by
+// exactly one lane: the lane whose range holds its start.
+//
+// Each chunk runs three phases:
+//   A. every lane walks its range, counts the pattern ids it must report and
+//      keeps its first few occurrences in registers;
+//   B. a workgroup prefix sum orders the lanes' counts, and a decoupled
+//      look-back over the previous chunks' published counts gives the chunk's
+//      offset in the text's output, so the global list comes out sorted with
+//      no sort pass (the paper sums per-thread counts on the host, Section 6,
+//      GPU-U stage; here the sum becomes the output offset);
+//   C. lanes write their (position, id) pairs at their offsets; a lane with
+//      more occurrences than its registers hold walks its range again.
+//
+// Walkers:
+//   AC - one dependent lookup per byte in the dense table (Section 3.1, array
+//        form of the goto function with supply transitions precomputed); the
+//        table sits in LDS when it fits, otherwise it is read through L2.
+//        Text bytes are read by each lane with 16-byte loads, one 64-byte
+//        block ahead of use.
+//   WM - the chunk's text is staged in LDS with 16-byte coalesced loads
+//        (Section 4.2.2, collective reads into shared memory); each lane then
+//        runs the Wu-Manber window loop (Section 3.2, Algorithm 5) over its
+//        window ends with SHIFT in LDS or L2, and verifies candidate windows
+//        against HASH/PREFIX and the pattern bytes.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include "mpm_internal.h"
+
+namespace mpm {
+
+// Address-space qualified pointers: LDS tables must be read with ds_read and
+// global data with global_load (a generic pointer would give flat loads).
+#define LDS_AS __attribute__((address_space(3)))
+#define GLB_AS __attribute__((address_space(1)))
+template <typename T> using lds_cptr = const LDS_AS T *;
+template <typename T> using glb_cptr = const GLB_AS T *;
+template <bool InLds, typename T> struct TabPtr { using type = glb_cptr<T>; };
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte load/store unit
+template <typename T> struct TabPtr<true, T> { using type = lds_cptr<T>; };
+
+static const int K_SLOTS = 4;  // occurrences a lane keeps in registers
+static const uint32_t SPIN_LIMIT = 1u << 24;
+
+// ---------------------------------------------------------------------------
+// Look-back status words
+// ---------------------------------------------------------------------------
+// A status word carries its flag and its value together, so no other memory
+// is published through it: relaxed device-coherent atomics suffice. (Acquire
+// or release at device scope would write back or invalidate the L2 of every
+// chunk's XCD, which costs far more than the scan of a chunk.)
+__device__ __forceinline__ uint64_t ld_status(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t make_status(uint32_t epoch, uint32_t flag, uint64_t val)
+{
+    return ((uint64_t)(epoch & ST_EPOCH_MASK) << 38) | ((uint64_t)flag << ST_VAL_BITS) |
+           (val & ST_VAL_MASK);
+}
+
+// Publish this chunk's count and return the sum of all earlier chunks of the
+// same text (decoupled look-back). flag 1: this chunk's count only; flag 2:
+// inclusive prefix. Run by the 64 lanes of wave 0: each probe reads the 64
+// preceding status words at once and stops at the nearest inclusive one.
+// Chunks before the text's first chunk count as an inclusive zero.
+__device__ __forceinline__ uint64_t look_back(uint64_t *status, uint64_t g, uint64_t first_g, uint64_t agg,
+                              uint32_t epoch, uint32_t *err)
+{
+    const int lane = threadIdx.x & 63;
+    if (g == first_g) {
+        if (lane == 0)
+            st_status(&status[g], make_status(epoch, 2, agg));
+        return 0;
+    }
+    if (lane == 0)
+        st_status(&status[g], make_status(epoch, 1, agg));
+    const uint64_t tag = epoch & ST_EPOCH_MASK;
+    uint64_t excl = 0;
+    int64_t top = (int64_t)g - 1;  // status index probed by lane 0
+    uint32_t spins = 0;
+    while (true) {
+        const int64_t j = top - lane;
+        uint32_t fl = 2;
+        uint64_t val = 0;
+        if (j >= (int64_t)first_g) {
+            const uint64_t v = ld_status(&status[j]);
+            fl = ((v >> 38) == tag) ? ((uint32_t)(v >> ST_VAL_BITS) & 3u) : 0u;
+            val = v & ST_VAL_MASK;
+        }
+        const uint64_t ready = __ballot(fl != 0);
+        const uint64_t incl = __ballot(fl == 2);
+        const int k = incl ? __ffsll((long long)incl) - 1 : 64;      // nearest inclusive lane
+        const uint64_t need = k >= 63 ? ~0ull : ((2ull << k) - 1);   // lanes 0..k
+        if ((ready & need) != need) {
+            if (++spins > SPIN_LIMIT) {  // never expected; keeps every wave finite
+                if (lane == 0)
+                    atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t x = lane <= k ? val : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            x += __shfl_xor(x, o, 64);
+        excl += x;
+        if (k < 64)
+            break;
+        top -= 64;
+    }
+    if (lane == 0)
+        st_status(&status[g], make_status(epoch, 2, excl + agg));
+    return excl;
+}
+
+// Offsets of a chunk's virtual lanes in the text's output. A chunk holds
+// I * W virtual lanes in text order; lane t runs virtual lanes t, t + W, ...
+// cnt[v] is the number of pairs of this lane's v-th virtual lane; ob[v]
+// receives its first output index. s_scan holds I * (W / 64) + 1 words.
+template <int W, int I>
+__device__ __forceinline__ void chunk_offsets(const uint32_t (&cnt)[I], uint64_t (&ob)[I],
+                                              uint64_t *s_scan, uint64_t *status, uint64_t g,
+                                              uint64_t first_g, bool last, uint64_t *total,
+                                              uint32_t epoch, uint32_t *err)
+{
+    constexpr int NW = W / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x[I];
+#pragma unroll
+    for (int v = 0; v < I; ++v)
+        x[v] = cnt[v];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int v = 0; v < I; ++v) {
+            const uint32_t y = __shfl_up(x[v], o, 64);
+            if (lane >= o)
+                x[v] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int v = 0; v < I; ++v)
+            s_scan[v * NW + wave] = x[v];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint64_t run = 0;
+        for (int w = 0; w < I * NW; ++w)
+            run += s_scan[w];
+        const uint64_t excl = look_back(status, g, first_g, run, epoch, err);
+        if (lane == 0) {
+            uint64_t r = 0;
+            for (int w = 0; w < I * NW; ++w) {
+                const uint64_t t = s_scan[w];
+                s_scan[w] = r;
+                r += t;
+            }
+            s_scan[I * NW] = excl;
+            if (last)
+                *total = excl + run;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < I; ++v)
+        ob[v] = s_scan[I * NW] + s_scan[v * NW + wave] + (x[v] - cnt[v]);
+}
+
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_t &ob, uint32_t pos,
+                                          uint32_t u, const GLB_AS uint32_t *uoff,
+                                          const GLB_AS uint32_t *uids, uint32_t dupfree)
+{
+    GLB_AS v2u *out = (GLB_AS v2u *)out_;
+    if (dupfree) {
+        if (ob < cap)
+            out[ob] = v2u{pos, uids[u]};
+        ++ob;
+        return;
+    }
+    const uint32_t b = uoff[u], e = uoff[u + 1];
+    for (uint32_t j = b; j < e; ++j) {
+        if (ob < cap)
+            out[ob] = v2u{pos, uids[j]};
+        ++ob;
+    }
+}
+
+// Cooperative global -> LDS copy (bytes multiple of 16, both 16-aligned).
+template <int W>
+__device__ __forceinline__ void copy_to_lds(uint8_t *dst, const uint8_t *src, uint32_t bytes)
+{
+    glb_cptr<v4u> s = (glb_cptr<v4u>)src;
+    LDS_AS v4u *d = (LDS_AS v4u *)dst;
+    for (uint32_t k = threadIdx.x; k < bytes / 16; k += W)
+        d[k] = s[k];
+}
+
+// Stream bytes [p, end) of a text through registers: single bytes up to a
+// 16-byte boundary, 16-byte pieces up to a 128-byte (cache line) boundary,
+// then whole lines (eight 16-byte loads issued together, the next line's
+// loads issued before the current one is consumed), then 16-byte pieces, then
+// bytes. Reading whole lines matters: with a thousand lanes per CU streaming
+// separate ranges, a line read in two halves is often evicted from L2 between
+// them and fetched from HBM twice. one(byte, pos) and sixteen(v4u, pos)
+// consume in text order.
+// prep(v4u) turns 16 loaded bytes into whatever the consumer keeps (the bytes
+// themselves, or something smaller); it runs on a whole line as soon as the
+// line is consumed, so only the prepared form stays live next to the
+// in-flight loads of the following line.
+template <class F1, class FP, class FU>
+__device__ __forceinline__ void stream_text(glb_cptr<uint8_t> text, uint64_t p, uint64_t end,
+                                            F1 &&one, FP &&prep, FU &&use)
+{
+    while (p < end && (((uintptr_t)(text + p)) & 15u)) {
+        one((uint32_t)text[p], p);
+        ++p;
+    }
+    while (p + 16 <= end && (((uintptr_t)(text + p)) & 127u)) {
+        use(prep(*(glb_cptr<v4u>)(text + p)), p);
+        p += 16;
+    }
+    if (p + 128 <= end) {
+        v4u c[8];
+        {
+            glb_cptr<v4u> q = (glb_cptr<v4u>)(text + p);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                c[j] = q[j];
+        }
+        while (true) {
+            decltype(prep(c[0])) t[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                t[j] = prep(c[j]);
+            const bool more = p + 256 <= end;
+            glb_cptr<v4u> nq = (glb_cptr<v4u>)(text + (more ? p + 128 : p));
+            v4u nx[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                nx[j] = nq[j];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                use(t[j], p + 16 * j);
+            p += 128;
+            if (!more)
+                break;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                c[j] = nx[j];
+        }
+    }
+    while (p + 16 <= end) {
+        use(prep(*(glb_cptr<v4u>)(text + p)), p);
+        p += 16;
+    }
+    while (p < end) {
+        one((uint32_t)text[p], p);
+        ++p;
+    }
+}
+
+template <class F1, class F16>
+__device__ __forceinline__ void stream_text(glb_cptr<uint8_t> text, uint64_t p, uint64_t end,
+                                            F1 &&one, F16 &&sixteen)
+{
+    stream_text(text, p, end, one, [](const v4u c) { return c; }, sixteen);
+}
+
+// ---------------------------------------------------------------------------
+// Aho-Corasick walker
+// ---------------------------------------------------------------------------
+// Column byte offsets of four text bytes at once (Swar variant): 3-bit codes
+// pick each byte's expected pattern byte and column through v_perm; a SWAR
+// zero-byte test sends every byte that is not its code's pattern byte to
+// column 0 (the root).
+__device__ __forceinline__ uint32_t swar_cols(uint32_t w, uint32_t sh, uint32_t pb_lo,
+                                              uint32_t pb_hi, uint32_t pc_lo, uint32_t pc_hi)
+{
+    const uint32_t code = (w >> sh) & 0x07070707u;
+    const uint32_t expect = __builtin_amdgcn_perm(pb_hi, pb_lo, code);
+    const uint32_t col = __builtin_amdgcn_perm(pc_hi, pc_lo, code);
+    const uint32_t x = w ^ expect;
+    const uint32_t nz = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;  // bit 7: byte != 0
+    return col & ~((nz >> 7) * 0xFFu);
+}
+
+template <typename St, bool InLds, bool Swar, int Ilp>
+struct AcWalk {
+    using Dev = AcDev;
+    static constexpr int ILP = Ilp;
+    typename TabPtr<InLds, uint8_t>::type dfab;  // table, addressed in bytes
+    lds_cptr<uint16_t> cls;                      // column byte offset per byte value
+    uint32_t rowb, first_term, m, sh, pb_lo, pb_hi, pc_lo, pc_hi;
+
+    template <int W>
+    __device__ __forceinline__ void setup(const AcDev &a, uint8_t *smem, uint32_t /*unused*/)
+    {
+        rowb = a.cp * (uint32_t)sizeof(St);
+        first_term = a.first_term;
+        m = a.m;
+        sh = a.swar_shift;
+        pb_lo = a.perm_byte_lo;
+        pb_hi = a.perm_byte_hi;
+        pc_lo = a.perm_col_lo;
+        pc_hi = a.perm_col_hi;
+        copy_to_lds<W>(smem, a.cls, 512);
+        cls = (lds_cptr<uint16_t>)smem;
+        if (InLds) {
+            copy_to_lds<W>(smem + 512, (const uint8_t *)a.dfa, a.dfa_bytes);
+            dfab = (typename TabPtr<InLds, uint8_t>::type)(smem + 512);
+        } else {
+            dfab = (typename TabPtr<InLds, uint8_t>::type)a.dfa;
+        }
+        __syncthreads();
+    }
+
+    // One transition: row s, column at byte offset coloff.
+    __device__ __forceinline__ uint32_t next(uint32_t s, uint32_t coloff) const
+    {
+        const uint32_t off = sizeof(St) == 2 ? __umul24(s, rowb) + coloff : s * rowb + coloff;
+        return *(typename TabPtr<InLds, St>::type)(dfab + off);
+    }
+
+    // Byte-offset columns of the 16 bytes of c.
+    __device__ __forceinline__ void cols16(const v4u c, uint32_t (&cw)[4]) const
+    {
+        if (Swar) {
+            cw[0] = swar_cols(c.x, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+            cw[1] = swar_cols(c.y, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+            cw[2] = swar_cols(c.z, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+            cw[3] = swar_cols(c.w, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+        } else {
+            cw[0] = c.x;
+            cw[1] = c.y;
+            cw[2] = c.z;
+            cw[3] = c.w;
+        }
+    }
+
+    __device__ __forceinline__ uint32_t col_of(const uint32_t (&cw)[4], int k) const
+    {
+        const uint32_t byte = (cw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+        return Swar ? byte : (uint32_t)cls[byte];
+    }
+
+    template <class F>
+    __device__ __forceinline__ void report16(const uint32_t (&st)[16], uint32_t mx, uint64_t q,
+                                             F &cb) const
+    {
+        if (mx >= first_term) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (st[k] >= first_term)
+                    cb(q + k + 1 - m, st[k] - first_term);
+        }
+    }
+
+    // Continue a walk in state s over bytes [p, end); cb(start, u) for every
+    // terminal state reached (start = index of the byte - m + 1).
+    template <class F>
+    __device__ __forceinline__ void walk_from(uint32_t &s, glb_cptr<uint8_t> text, uint64_t p,
+                                              uint64_t end, F &cb) const
+    {
+        stream_text(
+            text, p, end,
+            [&](uint32_t b, uint64_t q) {
+                s = next(s, cls[b]);
+                if (s >= first_term)
+                    cb(q + 1 - m, s - first_term);
+            },
+            [&](const v4u c, uint64_t q) {
+                uint32_t cw[4];
+                cols16(c, cw);
+                uint32_t st[16];
+                uint32_t mx = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    s = next(s, col_of(cw, k));
+                    st[k] = s;
+                    mx = max(mx, s);
+                }
+                report16(st, mx, q, cb);
+            });
+    }
+
+    template <class F>
+    __device__ __forceinline__ void walk(glb_cptr<uint8_t> text, uint64_t p, uint64_t end,
+                                         F &cb) const
+    {
+        uint32_t s = 0;
+        walk_from(s, text, p, end, cb);
+    }
+
+    // Two walks in lockstep (bytes [pa, ea) and [pb, eb), both starting on
+    // 16-byte boundaries): two independent lookup chains per lane. The common
+    // length runs interleaved with 16-byte loads two pieces ahead; the rest of
+    // each walk runs alone.
+    template <class FA, class FB>
+    __device__ __forceinline__ void walk2(glb_cptr<uint8_t> text, uint64_t pa, uint64_t ea,
+                                          uint64_t pb, uint64_t eb, FA &cba, FB &cbb) const
+    {
+        uint32_t sa = 0, sb = 0;
+        const uint64_t la = ea > pa ? ea - pa : 0, lb = eb > pb ? eb - pb : 0;
+        const uint64_t common = (la < lb ? la : lb) & ~15ull;
+        if (common) {
+            glb_cptr<v4u> qa = (glb_cptr<v4u>)(text + pa);
+            glb_cptr<v4u> qb = (glb_cptr<v4u>)(text + pb);
+            const uint64_t np = common / 16;
+            v4u a0 = qa[0], b0 = qb[0];
+            v4u a1 = qa[np > 1 ? 1 : 0], b1 = qb[np > 1 ? 1 : 0];
+            for (uint64_t k = 0; k < np; ++k) {
+                const uint64_t k2 = k + 2 < np ? k + 2 : k;
+                const v4u a2 = qa[k2], b2 = qb[k2];
+                uint32_t cwa[4], cwb[4];
+                cols16(a0, cwa);
+                cols16(b0, cwb);
+                uint32_t sta[16], stb[16];
+                uint32_t mxa = 0, mxb = 0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    sa = next(sa, col_of(cwa, j));
+                    sb = next(sb, col_of(cwb, j));
+                    sta[j] = sa;
+                    stb[j] = sb;
+                    mxa = max(mxa, sa);
+                    mxb = max(mxb, sb);
+                }
+                report16(sta, mxa, pa + 16 * k, cba);
+                report16(stb, mxb, pb + 16 * k, cbb);
+                a0 = a1;
+                a1 = a2;
+                b0 = b1;
+                b1 = b2;
+            }
+        }
+        walk_from(sa, text, pa + common, ea, cba);
+        walk_from(sb, text, pb + common, eb, cbb);
+    }
+
+    // Lane range: starts [lo, hi) relative to the chunk at text offset base.
+    template <class F>
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        if (lo >= hi)
+            return;
+        uint64_t end = base + hi + m - 1;
+        if (end > n)
+            end = n;
+        walk(text, base + lo, end, cb);
+    }
+
+    // Two lane ranges of the same chunk walked in lockstep (text 16-byte
+    // aligned), or one after the other.
+    template <class FA, class FB>
+    __device__ __forceinline__ void lane2(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                          uint32_t lo0, uint32_t hi0, uint32_t lo1, uint32_t hi1,
+                                          FA &&cba, FB &&cbb) const
+    {
+        if (lo1 >= hi1 || (((uintptr_t)text) & 15u)) {
+            lane(text, n, base, lo0, hi0, cba);
+            lane(text, n, base, lo1, hi1, cbb);
+            return;
+        }
+        uint64_t ea = base + hi0 + m - 1, eb = base + hi1 + m - 1;
+        if (ea > n)
+            ea = n;
+        if (eb > n)
+            eb = n;
+        walk2(text, base + lo0, ea, base + lo1, eb, cba, cbb);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Wu-Manber walker
+// ---------------------------------------------------------------------------
+static const int WM_QUEUE = 4;  // filtered candidates kept before exact checks
+
+// 2-bit codes of four bytes, first byte in the low bits.
+__device__ __forceinline__ uint32_t codes4(uint32_t w, uint32_t sh)
+{
+    uint32_t x = (w >> sh) & 0x03030303u;
+    x = (x | (x >> 6)) & 0x000F000Fu;
+    return (x | (x >> 12)) & 0xFFu;
+}
+
+template <bool InLds>
+struct WmWalk {
+    using Dev = WmDev;
+    static constexpr int ILP = 1;
+    typename TabPtr<InLds, uint16_t>::type sh16;
+    typename TabPtr<InLds, uint32_t>::type boff, bkey, bu;
+    glb_cptr<uint8_t> pats;
+    uint32_t m, B, csh, kl, hmask, kmask;
+
+    template <int W>
+    __device__ __forceinline__ void setup(const WmDev &a, uint8_t *smem, uint32_t /*unused*/)
+    {
+        m = a.m;
+        B = a.B;
+        csh = a.code_shift;
+        kl = a.key_len;
+        hmask = (1u << (2 * B)) - 1u;
+        kmask = kl >= 16 ? 0xffffffffu : ((1u << (2 * kl)) - 1u);
+        const uint8_t *base = a.tables;
+        if (InLds) {
+            copy_to_lds<W>(smem, a.tables, a.table_bytes);
+            base = smem;
+        }
+        sh16 = (typename TabPtr<InLds, uint16_t>::type)base;
+        boff = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_boff);
+        bkey = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bkey);
+        bu = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bu);
+        pats = (glb_cptr<uint8_t>)a.pats;
+        __syncthreads();
+    }
+
+    // 32 bits of the 96-bit history {h2:h1:h0} from bit o (o <= 64).
+    __device__ __forceinline__ static uint32_t bits(uint32_t h0, uint32_t h1, uint32_t h2, uint32_t o)
+    {
+        const uint32_t q = o >> 5;
+        const uint32_t lo = q == 0 ? h0 : (q == 1 ? h1 : h2);
+        const uint32_t hi = q == 0 ? h1 : h2;
+        return __builtin_amdgcn_alignbit(hi, lo, o & 31u);
+    }
+
+    // Window loop (Algorithm 5) over one lane's range, the text streamed
+    // through registers. The history keeps the 2-bit codes of the last 48
+    // characters read (positions [e-48, e), position q at bit 2(q-e+48)).
+    // Every window end nx < e is examined: the hash of its last B
+    // characters picks SHIFT; a zero shift sends the window to its bucket,
+    // where the filter key (codes of the key_len characters before the block)
+    // must equal the candidate's before the window is compared byte by byte
+    // with the pattern.
+    template <class F>
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        if (lo >= hi)
+            return;
+        // Texts are shorter than 2^32 bytes: positions fit in 32 bits.
+        const uint32_t p = (uint32_t)(base + lo);
+        uint64_t end64 = base + hi + m - 1;
+        if (end64 > n)
+            end64 = n;
+        const uint32_t end = (uint32_t)end64;
+        uint32_t nx = p + m - 1;
+        uint32_t e = p;
+        uint32_t h0 = 0, h1 = 0, h2 = 0;
+        uint32_t qn = 0;
+        uint32_t qp[WM_QUEUE];  // window ends
+        uint32_t qu[WM_QUEUE];
+#pragma unroll
+        for (int k = 0; k < WM_QUEUE; ++k) {
+            qp[k] = 0;
+            qu[k] = 0;
+        }
+        auto flush = [&]() {
+#pragma unroll
+            for (int k = 0; k < WM_QUEUE; ++k) {
+                if ((uint32_t)k < qn) {
+                    const uint64_t st = (uint64_t)qp[k] + 1 - m;
+                    glb_cptr<uint8_t> pp = pats + (uint64_t)qu[k] * m;
+                    bool ok = true;
+                    for (uint32_t j = 0; j < m; ++j)
+                        if (pp[j] != text[st + j]) {
+                            ok = false;
+                            break;
+                        }
+                    if (ok)
+                        cb(st, qu[k]);
+                }
+            }
+            qn = 0;
+        };
+        auto windows = [&]() {
+            while (nx < e) {
+                const uint32_t o = 2u * (nx + 49 - e - B);
+                const uint32_t h = bits(h0, h1, h2, o) & hmask;
+                const uint32_t sv = sh16[h];
+                if (sv & 0x8000u) {
+                    const uint32_t b = sv & 0x7fffu;
+                    const uint32_t key = kl ? (bits(h0, h1, h2, o - 2u * kl) & kmask) : 0u;
+                    const uint32_t je = boff[b + 1];
+                    for (uint32_t j = boff[b]; j < je; ++j) {
+                        if (bkey[j] == key) {
+                            if (qn == (uint32_t)WM_QUEUE)
+                                flush();
+#pragma unroll
+                            for (int k = 0; k < WM_QUEUE; ++k)
+                                if (qn == (uint32_t)k) {
+                                    qp[k] = nx;
+                                    qu[k] = bu[j];
+                                }
+                            ++qn;
+                        }
+                    }
+                    nx += 1;
+                } else {
+                    nx += sv;
+                }
+            }
+        };
+        stream_text(
+            text, p, end,
+            [&](uint32_t b, uint64_t) {
+                h0 = (h0 >> 2) | (h1 << 30);
+                h1 = (h1 >> 2) | (h2 << 30);
+                h2 = (h2 >> 2) | (((b >> csh) & 3u) << 30);
+                e += 1;
+                windows();
+            },
+            [&](const v4u c) {
+                return codes4(c.x, csh) | (codes4(c.y, csh) << 8) | (codes4(c.z, csh) << 16) |
+                       (codes4(c.w, csh) << 24);
+            },
+            [&](uint32_t codes, uint64_t) {
+                h0 = h1;
+                h1 = h2;
+                h2 = codes;
+                e += 16;
+                windows();
+            });
+        flush();
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Persistent chunk driver
+// ---------------------------------------------------------------------------
+template <class Walk, int W>
+__global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev sd,
+                                                 const uint32_t *uoff_, const uint32_t *uids_,
+                                                 uint32_t dupfree, uint32_t unused)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ TextDesc s_td;
+    __shared__ uint64_t s_tile;
+    __shared__ uint32_t s_epoch;
+    __shared__ uint64_t s_scan[Walk::ILP * (W / 64) + 1];
+
+    // Launch constants as plain values (no by-reference use of the argument
+    // structs, which would place them in private memory).
+    const uint32_t ntexts = sd.ntexts;
+    const uint64_t ntiles = sd.ntiles;
+    const uint32_t L = sd.lane_bytes;
+    uint32_t *const hdr = sd.hdr;
+    uint64_t *const status = sd.status;
+    const TextDesc *const multi = sd.multi;
+    glb_cptr<uint32_t> uoff = (glb_cptr<uint32_t>)uoff_;
+    glb_cptr<uint32_t> uids = (glb_cptr<uint32_t>)uids_;
+    const uint32_t m = a.m;
+    const uint64_t chunk = (uint64_t)W * L * Walk::ILP;
+
+    Walk wk;
+    wk.template setup<W>(a, smem, unused);
+    if (threadIdx.x == 0)
+        s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+    while (true) {
+        if (threadIdx.x == 0) {
+            const uint64_t t = atomicAdd(&hdr[WS_TICKET], 1u);
+            s_tile = t;
+            if (t < ntiles) {
+                if (ntexts == 1) {
+                    s_td = sd.single;
+                } else {  // the text whose chunk range holds t
+                    uint32_t lo = 0, hi = ntexts;
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (multi[mid].tile_begin <= t)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    s_td = multi[lo];
+                }
+            }
+        }
+        __syncthreads();
+        const uint64_t g = s_tile;
+        if (g >= ntiles)
+            break;
+        glb_cptr<uint8_t> text = (glb_cptr<uint8_t>)s_td.text;
+        const uint64_t n = s_td.n;
+        mpm_match *const out = s_td.out;
+        const uint64_t cap = s_td.cap;
+        uint64_t *const total = s_td.total;
+        const uint64_t first_g = s_td.tile_begin;
+        const uint64_t nt = s_td.ntiles;
+        const uint32_t epoch = s_epoch;
+        const uint64_t lt = g - first_g;
+        const uint64_t ns = n - m + 1;
+        const uint64_t base = lt * chunk;
+        const uint64_t starts = (ns - base) < chunk ? (ns - base) : chunk;
+
+        // Virtual lane v of this thread owns starts [lo[v], hi[v]) of the chunk.
+        constexpr int I = Walk::ILP;
+        constexpr int KS = I == 1 ? K_SLOTS : 2;  // occurrences kept per virtual lane
+        uint32_t lo[I], hi[I];
+#pragma unroll
+        for (int v = 0; v < I; ++v) {
+            const uint32_t l0 = (threadIdx.x + v * W) * L;
+            lo[v] = l0 < starts ? l0 : (uint32_t)starts;
+            hi[v] = (l0 + L) < starts ? (l0 + L) : (uint32_t)starts;
+        }
+
+        // Phase A: count and keep the first occurrences.
+        uint32_t nu[I], nid[I];
+        uint32_t so[I][KS], su[I][KS];
+#pragma unroll
+        for (int v = 0; v < I; ++v) {
+            nu[v] = 0;
+            nid[v] = 0;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) {
+                so[v][k] = 0;
+                su[v][k] = 0;
+            }
+        }
+        auto rec0 = [&](uint64_t start, uint32_t u) {
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                if (nu[0] == (uint32_t)k) {
+                    so[0][k] = (uint32_t)start;
+                    su[0][k] = u;
+                }
+            ++nu[0];
+            nid[0] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
+        };
+        if constexpr (I == 1) {
+            wk.lane(text, n, base, lo[0], hi[0], rec0);
+        } else {
+            auto rec1 = [&](uint64_t start, uint32_t u) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    if (nu[I - 1] == (uint32_t)k) {
+                        so[I - 1][k] = (uint32_t)start;
+                        su[I - 1][k] = u;
+                    }
+                ++nu[I - 1];
+                nid[I - 1] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
+            };
+            wk.lane2(text, n, base, lo[0], hi[0], lo[I - 1], hi[I - 1], rec0, rec1);
+        }
+
+        // Phase B: offsets.
+        const bool last = lt + 1 == nt;
+        uint64_t ob[I];
+        chunk_offsets<W, I>(nid, ob, s_scan, status, g, first_g, last, total, epoch, &hdr[WS_ERR]);
+
+        // Phase C: ordered writes.
+#pragma unroll
+        for (int v = 0; v < I; ++v) {
+            if (nu[v] == 0)
+                continue;
+            uint64_t o = ob[v];
+            if (nu[v] <= (uint32_t)KS) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    if ((uint32_t)k < nu[v])
+                        write_ids(out, cap, o, so[v][k], su[v][k], uoff, uids, dupfree);
+            } else {
+                wk.lane(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
+                    write_ids(out, cap, o, (uint32_t)start, u, uoff, uids, dupfree);
+                });
+            }
+        }
+        __syncthreads();
+    }
+
+    if (threadIdx.x == 0) {
+        const uint32_t dn = atomicAdd(&hdr[WS_DONE], 1u);
+        if (dn == gridDim.x - 1) {
+            __hip_atomic_store(&hdr[WS_TICKET], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&hdr[WS_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&hdr[WS_EPOCH], s_epoch + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Launch helper shared by the per-family translation units
+// ---------------------------------------------------------------------------
+template <class Walk>
+static const void *pick_w(uint32_t W)
+{
+    switch (W) {
+    case 256: return (const void *)scan_kernel<Walk, 256>;
+    case 512: return (const void *)scan_kernel<Walk, 512>;
+    case 1024: return (const void *)scan_kernel<Walk, 1024>;
+    }
+    return nullptr;
+}
+
+template <class Walk>
+static hipError_t launch_w(const typename Walk::Dev &a, const LaunchCfg &c, const ScanDev &sd,
+                           const uint32_t *uoff, const uint32_t *uids, uint32_t dupfree,
+                           uint32_t tl, hipStream_t s)
+{
+    const dim3 grid(c.grid), block(c.block_threads);
+    switch (c.block_threads) {
+    case 256:
+        hipLaunchKernelGGL((scan_kernel<Walk, 256>), grid, block, c.lds_bytes, s, a, sd, uoff, uids,
+                           dupfree, tl);
+        break;
+    case 512:
+        hipLaunchKernelGGL((scan_kernel<Walk, 512>), grid, block, c.lds_bytes, s, a, sd, uoff, uids,
+                           dupfree, tl);
+        break;
+    default:
+        hipLaunchKernelGGL((scan_kernel<Walk, 1024>), grid, block, c.lds_bytes, s, a, sd, uoff,
+                           uids, dupfree, tl);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// Kernel families, one translation unit each.
+const void *wm_kernel(const LaunchCfg &c);
+hipError_t wm_launch(const WmDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
+
+}  // namespace mpm

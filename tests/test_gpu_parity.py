@@ -50,8 +50,8 @@ def assert_same(got, want, what=""):
         assert bad.size == 0, f"{what}: first mismatch at {bad[0]}: got {(gp[bad[0]], gi[bad[0]])} want {(wp[bad[0]], wi[bad[0]])}"
 
 
-VARIANTS = [dict(lane_bytes=L, block_threads=W, placement=P)
-            for L, W, P in itertools.product((16, 64, 256), (256, 512, 1024), (1, 2))]
+VARIANTS = [dict(lane_bytes=L, block_threads=W, placement=P, flags=F)
+            for L, W, P, F in itertools.product((16, 64, 256), (256, 512, 1024), (1, 2), (0, 1, 2, 3))]
 
 
 @pytest.fixture(scope="module")
@@ -115,7 +115,9 @@ def test_edge_cases(mpm, case, algo):
     ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
     for mis in (0, 3):
         for v in (dict(lane_bytes=16, block_threads=256), dict(lane_bytes=64, block_threads=1024),
-                  dict(lane_bytes=256, block_threads=512, placement=2)):
+                  dict(lane_bytes=256, block_threads=512, placement=2),
+                  dict(lane_bytes=32, block_threads=256, flags=2),
+                  dict(lane_bytes=128, block_threads=1024, flags=3)):
             say(f"[edge {name} n={len(T)} d={len(P)} m={P.shape[1]}] {algo} misalign={mis} {v}")
             got = gpu_pairs(mpm, ix, T, mpm.variant(**v), misalign=mis)
             assert_same(got, want, f"{name} {algo} mis={mis} {v}")
@@ -148,7 +150,8 @@ def test_repeat_determinism_and_workspace_reuse(mpm, small, algo):
     ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
     t = to_dev(text)
     for v in (mpm.variant(lane_bytes=16, block_threads=256, grid=7),
-              mpm.variant(lane_bytes=64, block_threads=1024)):
+              mpm.variant(lane_bytes=64, block_threads=1024),
+              mpm.variant(lane_bytes=48, block_threads=512, grid=5, flags=2)):
         sc = mpm.Scanner(ix, len(text), len(want[0]) + 10, v)
         for rep in range(6):
             say(f"[repeat] {algo} {v} rep={rep}")
