@@ -237,6 +237,28 @@ uint32_t mpm_batch_groups(const mpm_batch *b);
 void mpm_batch_free(mpm_batch *b);
 
 /* ---------------------------------------------------------------------- */
+/* Autotuning                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Time one request under one variant as it runs inside a batched launch:
+ * the text is queued `copies` times in a single batched launch (every copy
+ * writes the same output region and total, with identical values), the
+ * launch runs once to warm up and then `reps` times, and *ms_out receives the
+ * fastest launch in milliseconds (divide by copies for the per-request cost).
+ * Not a step of the paper's method: it feeds the exhaustive autotuner that
+ * picks each request's variant. d_work: device, 256-byte aligned, at least
+ * mpm_tune_work_bytes; its contents are overwritten. Waits for the launches.
+ * Errors: EINVAL, ESTATE, ETOOBIG, ENOMEM, EHIP. */
+mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n, uint32_t copies,
+                         const mpm_variant *v, mpm_match *d_out, uint64_t capacity, uint64_t *d_total,
+                         void *d_work, uint64_t work_bytes, uint32_t reps, void *stream,
+                         float *ms_out);
+
+/* Workspace bytes for mpm_tune_time (0 on invalid arguments). */
+uint64_t mpm_tune_work_bytes(const mpm_index *idx, uint64_t n, uint32_t copies,
+                             const mpm_variant *v);
+
+/* ---------------------------------------------------------------------- */
 /* Inspection (host-only; used by tests)                                   */
 /* ---------------------------------------------------------------------- */
 

@@ -678,13 +678,17 @@ mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n
 }  // extern "C"
 
 struct mpm_batch {
+    // One persistent launch per block size; its texts ordered by index and
+    // walker kind so that LDS tables are reused across consecutive chunks.
     struct Group {
-        const mpm_index *idx;
-        mpm_variant var;
-        LaunchCfg cfg;
-        std::vector<TextDesc> texts;
+        uint32_t W = 0;
+        uint32_t grid_req = 0;
+        uint32_t grid = 0;
+        uint32_t lds = 0;
+        std::vector<BatchText> texts;
+        std::vector<BatchIndex> idx;
         uint64_t ntiles = 0;
-        uint64_t desc_off = 0, work_off = 0;
+        uint64_t text_off = 0, idx_off = 0, work_off = 0;
     };
     std::vector<mpm_request> reqs;
     std::vector<Group> groups;
@@ -706,63 +710,101 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
     try {
         mpm_batch *b = new mpm_batch();
         b->reqs.assign(reqs, reqs + count);
-        std::map<std::tuple<const mpm_index *, uint32_t, uint32_t, uint32_t, uint32_t, int>, size_t>
-            key;
+        struct Item {
+            uint32_t req;
+            const mpm_index *ix;
+            LaunchCfg cfg;
+            uint32_t kind;
+        };
+        std::map<uint32_t, std::vector<Item>> byw;
         for (uint32_t k = 0; k < count; k++) {
             const mpm_request &r = reqs[k];
             if (!r.idx || !r.d_total || (r.n && !r.d_text) || (r.capacity && !r.d_out)) {
                 delete b;
                 return fail(MPM_EINVAL, "mpm_batch_plan: request %u has a null pointer", k);
             }
+            if (!r.idx->d_image) {
+                delete b;
+                return fail(MPM_ESTATE, "mpm_batch_plan: request %u: index not uploaded", k);
+            }
             if (r.n >= (1ull << 32)) {
                 delete b;
                 return fail(MPM_ETOOBIG, "mpm_batch_plan: request %u: n >= 2^32", k);
             }
-            uint64_t ns = n_starts(r.n, r.idx->m);
-            if (ns == 0) {
+            if (n_starts(r.n, r.idx->m) == 0) {
                 b->zero_totals.push_back(r.d_total);
                 continue;
             }
-            LaunchCfg cfg;
-            mpm_status st = resolve_variant(r.idx, &r.variant, 0, &cfg);
+            mpm_variant v = r.variant;
+            v.flags &= ~MPM_VARIANT_ILP2;  // batched walkers run one range per lane
+            Item it;
+            it.req = k;
+            it.ix = r.idx;
+            mpm_status st = resolve_variant(r.idx, &v, 0, &it.cfg);
             if (st) {
                 delete b;
                 return st;
             }
-            auto kk = std::make_tuple(r.idx, cfg.lane_bytes, cfg.block_threads, cfg.placement,
-                                      r.variant.grid, cfg.swar * 2 + (cfg.ilp == 2));
-            auto it = key.find(kk);
-            size_t gi;
-            if (it == key.end()) {
-                gi = b->groups.size();
-                key[kk] = gi;
-                mpm_batch::Group g;
-                g.idx = r.idx;
-                g.var = r.variant;
-                g.cfg = cfg;
-                b->groups.push_back(g);
-            } else {
-                gi = it->second;
-            }
-            mpm_batch::Group &g = b->groups[gi];
-            uint64_t tb = tile_bytes(g.cfg);
-            uint64_t nt = (ns + tb - 1) / tb;
-            if (tb * (uint64_t)r.idx->max_dup >= (1ull << ST_VAL_BITS)) {
+            if ((uint64_t)it.cfg.lane_bytes * it.cfg.block_threads * r.idx->max_dup >=
+                (1ull << ST_VAL_BITS)) {
                 delete b;
                 return fail(MPM_EUNSUPPORTED, "mpm_batch_plan: too many copies of one pattern");
             }
-            g.texts.push_back(TextDesc{r.d_text, r.n, r.d_out, r.capacity, r.d_total, g.ntiles, nt});
-            g.ntiles += nt;
+            it.kind = batch_kind(r.idx, it.cfg);
+            byw[it.cfg.block_threads].push_back(it);
+            if (r.variant.grid)
+                byw[it.cfg.block_threads].back().cfg.grid = r.variant.grid;
+        }
+        for (auto &kv : byw) {
+            std::vector<Item> &items = kv.second;
+            std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
+                if (x.ix != y.ix)
+                    return (uintptr_t)x.ix < (uintptr_t)y.ix;
+                return x.kind < y.kind;
+            });
+            mpm_batch::Group g;
+            g.W = kv.first;
+            std::map<const mpm_index *, uint32_t> slot;
+            for (const Item &it : items) {
+                const mpm_request &r = reqs[it.req];
+                auto f = slot.find(it.ix);
+                uint32_t si;
+                if (f == slot.end()) {
+                    si = (uint32_t)g.idx.size();
+                    slot[it.ix] = si;
+                    BatchIndex bi;
+                    memset(&bi, 0, sizeof bi);
+                    if (it.ix->algo == MPM_ALGO_AC)
+                        bi.ac = ac_dev(it.ix);
+                    else
+                        bi.wm = wm_dev(it.ix);
+                    g.idx.push_back(bi);
+                } else {
+                    si = f->second;
+                }
+                if (it.cfg.grid)
+                    g.grid_req = std::max(g.grid_req, it.cfg.grid);
+                const uint64_t tb = (uint64_t)it.cfg.lane_bytes * it.cfg.block_threads;
+                const uint64_t nt = (n_starts(r.n, it.ix->m) + tb - 1) / tb;
+                BatchText bt;
+                memset(&bt, 0, sizeof bt);
+                bt.td = TextDesc{r.d_text, r.n, r.d_out, r.capacity, r.d_total, g.ntiles, nt};
+                bt.index = si;
+                bt.kind = it.kind;
+                bt.lane_bytes = it.cfg.lane_bytes;
+                g.texts.push_back(bt);
+                g.ntiles += nt;
+                g.lds = std::max(g.lds, it.cfg.lds_bytes);
+            }
+            b->groups.push_back(std::move(g));
         }
         uint64_t off = 0;
         for (auto &g : b->groups) {
-            mpm_status st = resolve_variant(g.idx, &g.var, g.ntiles, &g.cfg);
-            if (st) {
-                delete b;
-                return st;
-            }
-            g.desc_off = off;
-            off = align_up(off + g.texts.size() * sizeof(TextDesc), 256);
+            g.grid = batch_grid(g.W, g.lds, g.ntiles, g.grid_req);
+            g.text_off = off;
+            off = align_up(off + g.texts.size() * sizeof(BatchText), 256);
+            g.idx_off = off;
+            off = align_up(off + g.idx.size() * sizeof(BatchIndex), 256);
             g.work_off = off;
             off = align_up(off + WS_HEADER_BYTES + 8 * g.ntiles, 256);
         }
@@ -789,12 +831,11 @@ mpm_status mpm_batch_upload(mpm_batch *b, void *d_buf, uint64_t bytes, void *str
         return fail(MPM_EINVAL, "mpm_batch_upload: buffer must be 256-byte aligned");
     if (bytes < b->bytes)
         return fail(MPM_ENOMEM, "mpm_batch_upload: buffer too small");
-    for (const auto &g : b->groups)
-        if (!g.idx->d_image)
-            return fail(MPM_ESTATE, "mpm_batch_upload: an index is not uploaded");
     std::vector<uint8_t> host(b->bytes, 0);
-    for (const auto &g : b->groups)
-        memcpy(host.data() + g.desc_off, g.texts.data(), g.texts.size() * sizeof(TextDesc));
+    for (const auto &g : b->groups) {
+        memcpy(host.data() + g.text_off, g.texts.data(), g.texts.size() * sizeof(BatchText));
+        memcpy(host.data() + g.idx_off, g.idx.data(), g.idx.size() * sizeof(BatchIndex));
+    }
     memcpy(host.data() + b->zero_off, b->zero_totals.data(), 8 * b->zero_totals.size());
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(d_buf, host.data(), b->bytes, hipMemcpyHostToDevice, s);
@@ -817,21 +858,15 @@ mpm_status mpm_batch_run(const mpm_batch *b, void *stream)
             return st;
     }
     for (const auto &g : b->groups) {
-        ScanDev sd;
-        memset(&sd, 0, sizeof sd);
-        if (g.texts.size() == 1) {
-            sd.single = g.texts[0];
-            sd.multi = nullptr;
-            sd.ntexts = 1;
-        } else {
-            sd.multi = (const TextDesc *)(b->d_buf + g.desc_off);
-            sd.ntexts = (uint32_t)g.texts.size();
-        }
-        sd.lane_bytes = g.cfg.lane_bytes;
-        sd.ntiles = g.ntiles;
-        sd.hdr = (uint32_t *)(b->d_buf + g.work_off);
-        sd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
-        mpm_status st = launch_scan(g.idx, g.cfg, sd, stream);
+        BatchDev bd;
+        memset(&bd, 0, sizeof bd);
+        bd.texts = (const BatchText *)(b->d_buf + g.text_off);
+        bd.idx = (const BatchIndex *)(b->d_buf + g.idx_off);
+        bd.ntexts = (uint32_t)g.texts.size();
+        bd.ntiles = g.ntiles;
+        bd.hdr = (uint32_t *)(b->d_buf + g.work_off);
+        bd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
+        mpm_status st = launch_batch(bd, g.W, g.grid, g.lds, stream);
         if (st)
             return st;
     }
@@ -881,6 +916,119 @@ mpm_status mpm_batch_replay(const mpm_batch *b, void *stream)
     if (e != hipSuccess)
         return fail(MPM_EHIP, "mpm_batch_replay: %s", hipGetErrorString(e));
     return MPM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning support
+// ---------------------------------------------------------------------------
+static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
+                              const mpm_variant *v, LaunchCfg *cfg, uint64_t *nt_copy,
+                              uint64_t *idx_off, uint64_t *work_off, uint64_t *bytes)
+{
+    if (!idx || copies == 0)
+        return fail(MPM_EINVAL, "mpm_tune: null index or zero copies");
+    mpm_variant w = v ? *v : mpm_variant{0, 0, 0, 0, 0};
+    w.flags &= ~MPM_VARIANT_ILP2;
+    mpm_status st = resolve_variant(idx, &w, 0, cfg);
+    if (st)
+        return st;
+    const uint64_t tb = (uint64_t)cfg->lane_bytes * cfg->block_threads;
+    *nt_copy = (n_starts(n, idx->m) + tb - 1) / tb;
+    *idx_off = align_up((uint64_t)copies * sizeof(BatchText), 256);
+    *work_off = align_up(*idx_off + sizeof(BatchIndex), 256);
+    *bytes = *work_off + WS_HEADER_BYTES + 8 * (*nt_copy) * copies;
+    return MPM_OK;
+}
+
+uint64_t mpm_tune_work_bytes(const mpm_index *idx, uint64_t n, uint32_t copies,
+                             const mpm_variant *v)
+{
+    LaunchCfg cfg;
+    uint64_t nt, io, wo, bytes;
+    if (tune_layout(idx, n, copies, v, &cfg, &nt, &io, &wo, &bytes))
+        return 0;
+    return bytes;
+}
+
+mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n, uint32_t copies,
+                         const mpm_variant *v, mpm_match *d_out, uint64_t capacity, uint64_t *d_total,
+                         void *d_work, uint64_t work_bytes, uint32_t reps, void *stream,
+                         float *ms_out)
+{
+    if (!idx || !d_text || !d_total || !d_work || !ms_out || (capacity && !d_out) || reps == 0)
+        return fail(MPM_EINVAL, "mpm_tune_time: null argument");
+    if (!idx->d_image)
+        return fail(MPM_ESTATE, "mpm_tune_time: index not uploaded");
+    if (n >= (1ull << 32))
+        return fail(MPM_ETOOBIG, "mpm_tune_time: n >= 2^32");
+    if (((uintptr_t)d_work) & 255)
+        return fail(MPM_EINVAL, "mpm_tune_time: workspace must be 256-byte aligned");
+    LaunchCfg cfg;
+    uint64_t nt, io, wo, bytes;
+    mpm_status st = tune_layout(idx, n, copies, v, &cfg, &nt, &io, &wo, &bytes);
+    if (st)
+        return st;
+    if (work_bytes < bytes)
+        return fail(MPM_ENOMEM, "mpm_tune_time: workspace of %llu bytes, need %llu",
+                    (unsigned long long)work_bytes, (unsigned long long)bytes);
+    if (nt == 0) {
+        *ms_out = 0.f;
+        return MPM_OK;
+    }
+    try {
+        std::vector<uint8_t> host(wo + WS_HEADER_BYTES, 0);
+        BatchText *bt = (BatchText *)host.data();
+        for (uint32_t k = 0; k < copies; k++) {
+            // every copy writes the same region: identical values, one total
+            bt[k].td = TextDesc{d_text, n, d_out, capacity, d_total, (uint64_t)k * nt, nt};
+            bt[k].index = 0;
+            bt[k].kind = batch_kind(idx, cfg);
+            bt[k].lane_bytes = cfg.lane_bytes;
+        }
+        BatchIndex *bi = (BatchIndex *)(host.data() + io);
+        if (idx->algo == MPM_ALGO_AC)
+            bi->ac = ac_dev(idx);
+        else
+            bi->wm = wm_dev(idx);
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = hipMemcpyAsync(d_work, host.data(), host.size(), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return fail(MPM_EHIP, "mpm_tune_time: upload: %s", hipGetErrorString(e));
+        const uint64_t ntiles = nt * copies;
+        BatchDev bd;
+        memset(&bd, 0, sizeof bd);
+        bd.texts = (const BatchText *)d_work;
+        bd.idx = (const BatchIndex *)((uint8_t *)d_work + io);
+        bd.ntexts = copies;
+        bd.ntiles = ntiles;
+        bd.hdr = (uint32_t *)((uint8_t *)d_work + wo);
+        bd.status = (uint64_t *)((uint8_t *)d_work + wo + WS_HEADER_BYTES);
+        const uint32_t grid = batch_grid(cfg.block_threads, cfg.lds_bytes, ntiles,
+                                         v ? v->grid : 0);
+        hipEvent_t a, z;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&z) != hipSuccess)
+            return fail(MPM_EHIP, "mpm_tune_time: event creation failed");
+        float best = 1e30f;
+        st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);  // warm-up
+        for (uint32_t r = 0; r < reps && st == MPM_OK; r++) {
+            (void)hipEventRecord(a, s);
+            st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);
+            (void)hipEventRecord(z, s);
+            if (st == MPM_OK && hipEventSynchronize(z) == hipSuccess) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, a, z);
+                best = std::min(best, ms);
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(z);
+        if (st)
+            return st;
+        *ms_out = best;
+        return MPM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPM_ENOMEM, "mpm_tune_time: out of host memory");
+    }
 }
 
 void mpm_batch_free(mpm_batch *b)

@@ -92,6 +92,42 @@ struct ScanDev {
     uint64_t *status;
 };
 
+// Batched launches: one descriptor per text (in queue order) and one per
+// index. kind selects the walker; BK_SWAR marks AC byte classes computed in
+// registers.
+enum {
+    BK_AC16_LDS = 0,
+    BK_AC16_GLB = 1,
+    BK_AC32_GLB = 2,
+    BK_WM_LDS = 3,
+    BK_WM_GLB = 4,
+    BK_WALK_MASK = 0x7f,
+    BK_SWAR = 0x80
+};
+
+struct BatchIndex {
+    AcDev ac;
+    WmDev wm;
+};
+
+struct BatchText {
+    TextDesc td;
+    uint32_t index;       // into the launch's BatchIndex array
+    uint32_t kind;        // BK_*
+    uint32_t lane_bytes;
+    uint32_t pad;
+};
+
+struct BatchDev {
+    const BatchText *texts;
+    const BatchIndex *idx;
+    uint32_t ntexts;
+    uint32_t pad;
+    uint64_t ntiles;
+    uint32_t *hdr;
+    uint64_t *status;
+};
+
 // Look-back status word: [63:38] epoch, [37:36] flag, [35:0] value.
 static const uint64_t ST_VAL_BITS = 36;
 static const uint64_t ST_VAL_MASK = (1ull << ST_VAL_BITS) - 1;
@@ -153,4 +189,9 @@ mpm_status launch_scan(const mpm_index *idx, const LaunchCfg &cfg, const ScanDev
                        void *stream);
 mpm_status launch_zero_totals(uint64_t *const *d_totals_dev, uint32_t count, uint64_t *single,
                               void *stream);
+AcDev ac_dev(const mpm_index *ix);
+WmDev wm_dev(const mpm_index *ix);
+uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c);
+uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t grid_req);
+mpm_status launch_batch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds, void *stream);
 }  // namespace mpm

@@ -74,7 +74,7 @@ static DeviceLimits limits()
     return cache[dev];
 }
 
-static AcDev ac_dev(const mpm_index *ix)
+AcDev ac_dev(const mpm_index *ix)
 {
     AcDev a;
     a.dfa = ix->d_image + ix->off_a;
@@ -101,7 +101,7 @@ static AcDev ac_dev(const mpm_index *ix)
     return a;
 }
 
-static WmDev wm_dev(const mpm_index *ix)
+WmDev wm_dev(const mpm_index *ix)
 {
     WmDev a;
     a.tables = ix->d_image + ix->off_a;
@@ -206,6 +206,43 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
     }
     if (e != hipSuccess)
         return fail(MPM_EHIP, "scan launch: %s", hipGetErrorString(e));
+    return MPM_OK;
+}
+
+uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c)
+{
+    uint32_t k;
+    if (ix->algo == MPM_ALGO_AC)
+        k = ix->state_bytes == 4 ? BK_AC32_GLB
+                                 : (c.placement == MPM_PLACE_LDS ? BK_AC16_LDS : BK_AC16_GLB);
+    else
+        k = c.placement == MPM_PLACE_LDS ? BK_WM_LDS : BK_WM_GLB;
+    return k | (c.swar ? (uint32_t)BK_SWAR : 0u);
+}
+
+uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t grid_req)
+{
+    const DeviceLimits lim = limits();
+    const void *k = batch_kernel_ptr(W);
+    if (lds_bytes > 65536)
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)W, lds_bytes);
+    if (e != hipSuccess || nb <= 0)
+        nb = 1;
+    uint64_t grid = grid_req ? grid_req : (uint64_t)nb * lim.cus;
+    if (grid > ntiles)
+        grid = ntiles;
+    return (uint32_t)(grid < 1 ? 1 : grid);
+}
+
+mpm_status launch_batch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds, void *stream)
+{
+    if (lds > 65536)
+        hipFuncSetAttribute(batch_kernel_ptr(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = batch_launch(bd, W, grid, lds, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(MPM_EHIP, "batch launch: %s", hipGetErrorString(e));
     return MPM_OK;
 }
 

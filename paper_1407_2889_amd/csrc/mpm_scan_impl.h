@@ -313,8 +313,16 @@ struct AcWalk {
     lds_cptr<uint16_t> cls;                      // column byte offset per byte value
     uint32_t rowb, first_term, m, sh, pb_lo, pb_hi, pc_lo, pc_hi;
 
+    // Copy what this walker reads from LDS (no barrier).
     template <int W>
-    __device__ __forceinline__ void setup(const AcDev &a, uint8_t *smem, uint32_t /*unused*/)
+    __device__ __forceinline__ static void load(const AcDev &a, uint8_t *smem)
+    {
+        copy_to_lds<W>(smem, a.cls, 512);
+        if (InLds)
+            copy_to_lds<W>(smem + 512, (const uint8_t *)a.dfa, a.dfa_bytes);
+    }
+
+    __device__ __forceinline__ void bind(const AcDev &a, uint8_t *smem)
     {
         rowb = a.cp * (uint32_t)sizeof(St);
         first_term = a.first_term;
@@ -324,14 +332,16 @@ struct AcWalk {
         pb_hi = a.perm_byte_hi;
         pc_lo = a.perm_col_lo;
         pc_hi = a.perm_col_hi;
-        copy_to_lds<W>(smem, a.cls, 512);
         cls = (lds_cptr<uint16_t>)smem;
-        if (InLds) {
-            copy_to_lds<W>(smem + 512, (const uint8_t *)a.dfa, a.dfa_bytes);
-            dfab = (typename TabPtr<InLds, uint8_t>::type)(smem + 512);
-        } else {
-            dfab = (typename TabPtr<InLds, uint8_t>::type)a.dfa;
-        }
+        dfab = InLds ? (typename TabPtr<InLds, uint8_t>::type)(smem + 512)
+                     : (typename TabPtr<InLds, uint8_t>::type)a.dfa;
+    }
+
+    template <int W>
+    __device__ __forceinline__ void setup(const AcDev &a, uint8_t *smem, uint32_t /*unused*/)
+    {
+        load<W>(a, smem);
+        bind(a, smem);
         __syncthreads();
     }
 
@@ -514,8 +524,15 @@ struct WmWalk {
     glb_cptr<uint8_t> pats;
     uint32_t m, B, csh, kl, hmask, kmask;
 
+    // Copy what this walker reads from LDS (no barrier).
     template <int W>
-    __device__ __forceinline__ void setup(const WmDev &a, uint8_t *smem, uint32_t /*unused*/)
+    __device__ __forceinline__ static void load(const WmDev &a, uint8_t *smem)
+    {
+        if (InLds)
+            copy_to_lds<W>(smem, a.tables, a.table_bytes);
+    }
+
+    __device__ __forceinline__ void bind(const WmDev &a, uint8_t *smem)
     {
         m = a.m;
         B = a.B;
@@ -523,16 +540,19 @@ struct WmWalk {
         kl = a.key_len;
         hmask = (1u << (2 * B)) - 1u;
         kmask = kl >= 16 ? 0xffffffffu : ((1u << (2 * kl)) - 1u);
-        const uint8_t *base = a.tables;
-        if (InLds) {
-            copy_to_lds<W>(smem, a.tables, a.table_bytes);
-            base = smem;
-        }
+        const uint8_t *base = InLds ? smem : a.tables;
         sh16 = (typename TabPtr<InLds, uint16_t>::type)base;
         boff = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_boff);
         bkey = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bkey);
         bu = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bu);
         pats = (glb_cptr<uint8_t>)a.pats;
+    }
+
+    template <int W>
+    __device__ __forceinline__ void setup(const WmDev &a, uint8_t *smem, uint32_t /*unused*/)
+    {
+        load<W>(a, smem);
+        bind(a, smem);
         __syncthreads();
     }
 
@@ -649,6 +669,118 @@ struct WmWalk {
 // ---------------------------------------------------------------------------
 // Persistent chunk driver
 // ---------------------------------------------------------------------------
+// One chunk (phases A-C). The chunk is chunk g of its text; base is its
+// first starting position, `starts` how many starting positions it holds.
+template <class Walk, int W>
+__device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> text, uint64_t n,
+                                              mpm_match *out, uint64_t cap, uint64_t *total,
+                                              uint64_t first_g, uint64_t nt, uint64_t g,
+                                              uint32_t L, uint32_t m, uint32_t epoch,
+                                              glb_cptr<uint32_t> uoff, glb_cptr<uint32_t> uids,
+                                              uint32_t dupfree, uint32_t *hdr, uint64_t *status,
+                                              uint64_t *s_scan)
+{
+    constexpr int I = Walk::ILP;
+    constexpr int KS = I == 1 ? K_SLOTS : 2;  // occurrences kept per virtual lane
+    const uint64_t chunk = (uint64_t)W * L * I;
+    const uint64_t lt = g - first_g;
+    const uint64_t ns = n - m + 1;
+    const uint64_t base = lt * chunk;
+    const uint64_t starts = (ns - base) < chunk ? (ns - base) : chunk;
+
+    // Virtual lane v of this thread owns starts [lo[v], hi[v]) of the chunk.
+    uint32_t lo[I], hi[I];
+#pragma unroll
+    for (int v = 0; v < I; ++v) {
+        const uint32_t l0 = (threadIdx.x + v * W) * L;
+        lo[v] = l0 < starts ? l0 : (uint32_t)starts;
+        hi[v] = (l0 + L) < starts ? (l0 + L) : (uint32_t)starts;
+    }
+
+    // Phase A: count and keep the first occurrences.
+    uint32_t nu[I], nid[I];
+    uint32_t so[I][KS], su[I][KS];
+#pragma unroll
+    for (int v = 0; v < I; ++v) {
+        nu[v] = 0;
+        nid[v] = 0;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            so[v][k] = 0;
+            su[v][k] = 0;
+        }
+    }
+    auto rec0 = [&](uint64_t start, uint32_t u) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            if (nu[0] == (uint32_t)k) {
+                so[0][k] = (uint32_t)start;
+                su[0][k] = u;
+            }
+        ++nu[0];
+        nid[0] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
+    };
+    if constexpr (I == 1) {
+        wk.lane(text, n, base, lo[0], hi[0], rec0);
+    } else {
+        auto rec1 = [&](uint64_t start, uint32_t u) {
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                if (nu[I - 1] == (uint32_t)k) {
+                    so[I - 1][k] = (uint32_t)start;
+                    su[I - 1][k] = u;
+                }
+            ++nu[I - 1];
+            nid[I - 1] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
+        };
+        wk.lane2(text, n, base, lo[0], hi[0], lo[I - 1], hi[I - 1], rec0, rec1);
+    }
+
+    // Phase B: offsets.
+    const bool last = lt + 1 == nt;
+    uint64_t ob[I];
+    chunk_offsets<W, I>(nid, ob, s_scan, status, g, first_g, last, total, epoch, &hdr[WS_ERR]);
+
+    // Phase C: ordered writes.
+#pragma unroll
+    for (int v = 0; v < I; ++v) {
+        if (nu[v] == 0)
+            continue;
+        uint64_t o = ob[v];
+        if (nu[v] <= (uint32_t)KS) {
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                if ((uint32_t)k < nu[v])
+                    write_ids(out, cap, o, so[v][k], su[v][k], uoff, uids, dupfree);
+        } else {
+            wk.lane(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
+                write_ids(out, cap, o, (uint32_t)start, u, uoff, uids, dupfree);
+            });
+        }
+    }
+}
+
+// Take a ticket (thread 0), returning it through LDS; the caller syncs.
+__device__ __forceinline__ uint64_t take_ticket(uint32_t *hdr)
+{
+    return atomicAdd(&hdr[WS_TICKET], 1u);
+}
+
+// Last workgroup to finish resets the ticket and done counters and moves the
+// epoch on, so the next launch on this workspace starts clean.
+__device__ __forceinline__ void finish_launch(uint32_t *hdr, uint32_t epoch)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t dn = atomicAdd(&hdr[WS_DONE], 1u);
+        if (dn == gridDim.x - 1) {
+            __hip_atomic_store(&hdr[WS_TICKET], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&hdr[WS_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&hdr[WS_EPOCH], epoch + 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <class Walk, int W>
 __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev sd,
                                                  const uint32_t *uoff_, const uint32_t *uids_,
@@ -671,7 +803,6 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     glb_cptr<uint32_t> uoff = (glb_cptr<uint32_t>)uoff_;
     glb_cptr<uint32_t> uids = (glb_cptr<uint32_t>)uids_;
     const uint32_t m = a.m;
-    const uint64_t chunk = (uint64_t)W * L * Walk::ILP;
 
     Walk wk;
     wk.template setup<W>(a, smem, unused);
@@ -680,7 +811,7 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
 
     while (true) {
         if (threadIdx.x == 0) {
-            const uint64_t t = atomicAdd(&hdr[WS_TICKET], 1u);
+            const uint64_t t = take_ticket(hdr);
             s_tile = t;
             if (t < ntiles) {
                 if (ntexts == 1) {
@@ -702,105 +833,141 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
         const uint64_t g = s_tile;
         if (g >= ntiles)
             break;
-        glb_cptr<uint8_t> text = (glb_cptr<uint8_t>)s_td.text;
-        const uint64_t n = s_td.n;
-        mpm_match *const out = s_td.out;
-        const uint64_t cap = s_td.cap;
-        uint64_t *const total = s_td.total;
-        const uint64_t first_g = s_td.tile_begin;
-        const uint64_t nt = s_td.ntiles;
-        const uint32_t epoch = s_epoch;
-        const uint64_t lt = g - first_g;
-        const uint64_t ns = n - m + 1;
-        const uint64_t base = lt * chunk;
-        const uint64_t starts = (ns - base) < chunk ? (ns - base) : chunk;
+        process_chunk<Walk, W>(wk, (glb_cptr<uint8_t>)s_td.text, s_td.n, s_td.out, s_td.cap,
+                               s_td.total, s_td.tile_begin, s_td.ntiles, g, L, m, s_epoch, uoff,
+                               uids, dupfree, hdr, status, s_scan);
+        __syncthreads();
+    }
+    finish_launch(hdr, s_epoch);
+}
 
-        // Virtual lane v of this thread owns starts [lo[v], hi[v]) of the chunk.
-        constexpr int I = Walk::ILP;
-        constexpr int KS = I == 1 ? K_SLOTS : 2;  // occurrences kept per virtual lane
-        uint32_t lo[I], hi[I];
-#pragma unroll
-        for (int v = 0; v < I; ++v) {
-            const uint32_t l0 = (threadIdx.x + v * W) * L;
-            lo[v] = l0 < starts ? l0 : (uint32_t)starts;
-            hi[v] = (l0 + L) < starts ? (l0 + L) : (uint32_t)starts;
-        }
+// ---------------------------------------------------------------------------
+// Batched persistent kernel: many texts, each scanned with its own index and
+// walker kind, in one launch. Texts are ordered by index in the queue, so a
+// workgroup reloads its LDS tables only when the index of its next chunk
+// differs from the one it holds.
+// ---------------------------------------------------------------------------
+template <class Walk, int W, class Dev>
+__device__ __forceinline__ void batch_chunk(const Dev &dev, uint8_t *smem, glb_cptr<uint8_t> text,
+                                            uint64_t n, mpm_match *out, uint64_t cap,
+                                            uint64_t *total, uint64_t first_g, uint64_t nt,
+                                            uint64_t g, uint32_t L, uint32_t epoch, uint32_t *hdr,
+                                            uint64_t *status, uint64_t *s_scan)
+{
+    Walk wk;
+    wk.bind(dev, smem);
+    process_chunk<Walk, W>(wk, text, n, out, cap, total, first_g, nt, g, L, dev.m, epoch,
+                           (glb_cptr<uint32_t>)dev.uoff, (glb_cptr<uint32_t>)dev.uids, dev.dupfree,
+                           hdr, status, s_scan);
+}
 
-        // Phase A: count and keep the first occurrences.
-        uint32_t nu[I], nid[I];
-        uint32_t so[I][KS], su[I][KS];
-#pragma unroll
-        for (int v = 0; v < I; ++v) {
-            nu[v] = 0;
-            nid[v] = 0;
-#pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                so[v][k] = 0;
-                su[v][k] = 0;
-            }
-        }
-        auto rec0 = [&](uint64_t start, uint32_t u) {
-#pragma unroll
-            for (int k = 0; k < KS; ++k)
-                if (nu[0] == (uint32_t)k) {
-                    so[0][k] = (uint32_t)start;
-                    su[0][k] = u;
+template <int W>
+__global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ BatchText s_bt;
+    __shared__ uint64_t s_tile;
+    __shared__ uint32_t s_epoch;
+    __shared__ uint64_t s_scan[W / 64 + 1];
+
+    const uint32_t ntexts = bd.ntexts;
+    const uint64_t ntiles = bd.ntiles;
+    uint32_t *const hdr = bd.hdr;
+    uint64_t *const status = bd.status;
+    const BatchText *const texts = bd.texts;
+    if (threadIdx.x == 0)
+        s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t loaded = 0xffffffffu;  // (index << 8) | kind held in LDS (uniform)
+
+    while (true) {
+        if (threadIdx.x == 0) {
+            const uint64_t t = take_ticket(hdr);
+            s_tile = t;
+            if (t < ntiles) {
+                uint32_t lo = 0, hi = ntexts;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (texts[mid].td.tile_begin <= t)
+                        lo = mid;
+                    else
+                        hi = mid;
                 }
-            ++nu[0];
-            nid[0] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
-        };
-        if constexpr (I == 1) {
-            wk.lane(text, n, base, lo[0], hi[0], rec0);
-        } else {
-            auto rec1 = [&](uint64_t start, uint32_t u) {
-#pragma unroll
-                for (int k = 0; k < KS; ++k)
-                    if (nu[I - 1] == (uint32_t)k) {
-                        so[I - 1][k] = (uint32_t)start;
-                        su[I - 1][k] = u;
-                    }
-                ++nu[I - 1];
-                nid[I - 1] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
-            };
-            wk.lane2(text, n, base, lo[0], hi[0], lo[I - 1], hi[I - 1], rec0, rec1);
-        }
-
-        // Phase B: offsets.
-        const bool last = lt + 1 == nt;
-        uint64_t ob[I];
-        chunk_offsets<W, I>(nid, ob, s_scan, status, g, first_g, last, total, epoch, &hdr[WS_ERR]);
-
-        // Phase C: ordered writes.
-#pragma unroll
-        for (int v = 0; v < I; ++v) {
-            if (nu[v] == 0)
-                continue;
-            uint64_t o = ob[v];
-            if (nu[v] <= (uint32_t)KS) {
-#pragma unroll
-                for (int k = 0; k < KS; ++k)
-                    if ((uint32_t)k < nu[v])
-                        write_ids(out, cap, o, so[v][k], su[v][k], uoff, uids, dupfree);
-            } else {
-                wk.lane(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
-                    write_ids(out, cap, o, (uint32_t)start, u, uoff, uids, dupfree);
-                });
+                s_bt = texts[lo];
             }
         }
         __syncthreads();
-    }
-
-    if (threadIdx.x == 0) {
-        const uint32_t dn = atomicAdd(&hdr[WS_DONE], 1u);
-        if (dn == gridDim.x - 1) {
-            __hip_atomic_store(&hdr[WS_TICKET], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&hdr[WS_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&hdr[WS_EPOCH], s_epoch + 1u, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t g = s_tile;
+        if (g >= ntiles)
+            break;
+        const uint32_t kind = s_bt.kind;
+        const uint32_t ix = s_bt.index;
+        const BatchIndex &bi = bd.idx[ix];
+        const uint32_t key = (ix << 8) | kind;
+        if (key != loaded) {
+            switch (kind & BK_WALK_MASK) {
+            case BK_AC16_LDS: AcWalk<uint16_t, true, false, 1>::load<W>(bi.ac, smem); break;
+            case BK_AC16_GLB: AcWalk<uint16_t, false, false, 1>::load<W>(bi.ac, smem); break;
+            case BK_AC32_GLB: AcWalk<uint32_t, false, false, 1>::load<W>(bi.ac, smem); break;
+            case BK_WM_LDS: WmWalk<true>::load<W>(bi.wm, smem); break;
+            default: break;
+            }
+            __syncthreads();
+            loaded = key;
         }
+        const uint32_t L = s_bt.lane_bytes;
+        glb_cptr<uint8_t> text = (glb_cptr<uint8_t>)s_bt.td.text;
+        const uint64_t n = s_bt.td.n;
+        mpm_match *const out = s_bt.td.out;
+        const uint64_t cap = s_bt.td.cap;
+        uint64_t *const total = s_bt.td.total;
+        const uint64_t first_g = s_bt.td.tile_begin;
+        const uint64_t nt = s_bt.td.ntiles;
+        const uint32_t epoch = s_epoch;
+        const bool swar = (kind & BK_SWAR) != 0;
+        switch (kind & BK_WALK_MASK) {
+        case BK_AC16_LDS:
+            if (swar)
+                batch_chunk<AcWalk<uint16_t, true, true, 1>, W>(bi.ac, smem, text, n, out, cap, total,
+                                                                first_g, nt, g, L, epoch, hdr,
+                                                                status, s_scan);
+            else
+                batch_chunk<AcWalk<uint16_t, true, false, 1>, W>(bi.ac, smem, text, n, out, cap,
+                                                                 total, first_g, nt, g, L, epoch,
+                                                                 hdr, status, s_scan);
+            break;
+        case BK_AC16_GLB:
+            if (swar)
+                batch_chunk<AcWalk<uint16_t, false, true, 1>, W>(bi.ac, smem, text, n, out, cap,
+                                                                 total, first_g, nt, g, L, epoch,
+                                                                 hdr, status, s_scan);
+            else
+                batch_chunk<AcWalk<uint16_t, false, false, 1>, W>(bi.ac, smem, text, n, out, cap,
+                                                                  total, first_g, nt, g, L, epoch,
+                                                                  hdr, status, s_scan);
+            break;
+        case BK_AC32_GLB:
+            if (swar)
+                batch_chunk<AcWalk<uint32_t, false, true, 1>, W>(bi.ac, smem, text, n, out, cap,
+                                                                 total, first_g, nt, g, L, epoch,
+                                                                 hdr, status, s_scan);
+            else
+                batch_chunk<AcWalk<uint32_t, false, false, 1>, W>(bi.ac, smem, text, n, out, cap,
+                                                                  total, first_g, nt, g, L, epoch,
+                                                                  hdr, status, s_scan);
+            break;
+        case BK_WM_LDS:
+            batch_chunk<WmWalk<true>, W>(bi.wm, smem, text, n, out, cap, total, first_g, nt, g, L,
+                                         epoch, hdr, status, s_scan);
+            break;
+        default:
+            batch_chunk<WmWalk<false>, W>(bi.wm, smem, text, n, out, cap, total, first_g, nt, g, L,
+                                          epoch, hdr, status, s_scan);
+            break;
+        }
+        __syncthreads();
     }
+    finish_launch(hdr, s_epoch);
 }
-
 
 // ---------------------------------------------------------------------------
 // Launch helper shared by the per-family translation units
@@ -840,6 +1007,9 @@ static hipError_t launch_w(const typename Walk::Dev &a, const LaunchCfg &c, cons
 }
 
 // Kernel families, one translation unit each.
+const void *batch_kernel_ptr(uint32_t W);
+hipError_t batch_launch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds,
+                        hipStream_t s);
 const void *wm_kernel(const LaunchCfg &c);
 hipError_t wm_launch(const WmDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 
