@@ -259,6 +259,46 @@ uint64_t mpm_tune_work_bytes(const mpm_index *idx, uint64_t n, uint32_t copies,
                              const mpm_variant *v);
 
 /* ---------------------------------------------------------------------- */
+/* Learned variant selector                                                */
+/* ---------------------------------------------------------------------- */
+
+/* A dense network predicts each scan variant's log-throughput from a
+ * request's features (7 -> 64 -> 64 -> 64 -> 24, ReLU on the hidden layers);
+ * it is trained on the autotuner's timings with these FP32 kernels. Not part
+ * of the paper's method: it chooses among launch variants that all return
+ * the same matches. Parameter vector (float, device): W1[7][64] b1[64]
+ * W2[64][64] b2[64] W3[64][64] b3[64] W4[64][24] b4[24], row-major, layer
+ * computing Z = A_prev W + b. All calls enqueue on `stream` and return. */
+#define MPM_MLP_IN 7
+#define MPM_MLP_HIDDEN 64
+#define MPM_MLP_OUT 24
+#define MPM_MLP_PARAMS 10392
+
+/* Floats of the activation buffer a forward pass of `batch` rows keeps. */
+uint64_t mpm_mlp_act_floats(uint32_t batch);
+
+/* d_x: batch x 7 features; d_act: mpm_mlp_act_floats(batch) floats
+ * (written, kept for the backward pass); d_y: batch x 24 outputs. */
+mpm_status mpm_mlp_forward(const float *d_theta, const float *d_x, uint32_t batch, float *d_act,
+                           float *d_y, void *stream);
+
+/* Masked mean squared error of d_y against d_t under d_mask (all batch x
+ * 24): *d_loss (device float, may be NULL) = sum M (Y-T)^2 / sum M, and
+ * d_dy = 2 M (Y-T) / sum M. */
+mpm_status mpm_mlp_loss_grad(const float *d_y, const float *d_t, const float *d_mask, uint32_t batch,
+                             float *d_dy, float *d_loss, void *stream);
+
+/* Gradient of the loss w.r.t. all parameters into d_grad (10,392 floats),
+ * given the forward pass's d_act and d_dy. d_tmp: 2 * batch * 64 floats. */
+mpm_status mpm_mlp_backward(const float *d_theta, const float *d_x, const float *d_act,
+                            const float *d_dy, uint32_t batch, float *d_grad, float *d_tmp,
+                            void *stream);
+
+/* One Adam step (t >= 1) on n parameters with moments d_m, d_v. */
+mpm_status mpm_mlp_adam(float *d_theta, const float *d_grad, float *d_m, float *d_v, uint32_t n,
+                        uint32_t t, float lr, float b1, float b2, float eps, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Inspection (host-only; used by tests)                                   */
 /* ---------------------------------------------------------------------- */
 

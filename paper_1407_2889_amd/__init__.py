@@ -121,6 +121,12 @@ _sig("mpm_read_probe", C.c_int32, [_vp, _u64, _vp, _vp])
 _sig("mpm_tune_time", C.c_int32, [_vp, _vp, _u64, _u32, C.POINTER(Variant), _vp, _u64, _vp, _vp,
                                   _u64, _u32, _vp, C.POINTER(C.c_float)])
 _sig("mpm_tune_work_bytes", _u64, [_vp, _u64, _u32, C.POINTER(Variant)])
+_sig("mpm_mlp_act_floats", _u64, [_u32])
+_sig("mpm_mlp_forward", C.c_int32, [_vp, _vp, _u32, _vp, _vp, _vp])
+_sig("mpm_mlp_loss_grad", C.c_int32, [_vp, _vp, _vp, _u32, _vp, _vp, _vp])
+_sig("mpm_mlp_backward", C.c_int32, [_vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp])
+_sig("mpm_mlp_adam", C.c_int32, [_vp, _vp, _vp, _vp, _u32, _u32, C.c_float, C.c_float, C.c_float,
+                                 C.c_float, _vp])
 
 # Every symbol include/mpm.h declares (checked by the CPU tests).
 EXPORTS = [
@@ -129,7 +135,8 @@ EXPORTS = [
     "mpm_batch_device_bytes", "mpm_batch_upload", "mpm_batch_run", "mpm_batch_capture",
     "mpm_batch_replay", "mpm_batch_groups", "mpm_batch_free", "mpm_export_ac",
     "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
-    "mpm_tune_time", "mpm_tune_work_bytes",
+    "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
+    "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam",
 ]
 
 

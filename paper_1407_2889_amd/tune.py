@@ -1,0 +1,176 @@
+"""Exhaustive autotuner for batched scans.
+
+Every request (one text, one pattern set) can be scanned by 24 launch
+variants: the algorithm (Aho-Corasick or Wu-Manber), the starting positions
+per lane (64, 256 or 1024), the workgroup size (256 or 512 threads) and the
+placement of the matching tables (LDS or global memory). All variants return
+the same matches; they differ only in speed. The exhaustive autotuner times
+all of them for a request the way it runs inside a batched launch
+(``mpm_tune_time``: the request is queued several times in one persistent
+launch so that small texts get a measurable, batch-realistic cost) and keeps
+the fastest. Variants that cannot run (tables too large for LDS) are marked
+invalid.
+
+Request features (inputs of the learned selector):
+    log2 n, log2 d, m, alphabet size (distinct pattern bytes), log2 of the
+    Aho-Corasick state count, Wu-Manber mean SHIFT, sampled match density
+    (matches per byte over the first 64 KiB of the text).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import (MPM_EUNSUPPORTED, MPM_OK, MpmError, PLACE_GLOBAL, PLACE_LDS, Index, Variant,
+               _check, _L, _stream_handle, _torch, build_ac, build_wm)
+
+ALGOS = ("ac", "wm")
+LANE_BYTES = (64, 256, 1024)
+BLOCK_THREADS = (256, 512)
+PLACEMENTS = (PLACE_LDS, PLACE_GLOBAL)
+
+# (algo, lane_bytes, block_threads, placement), 24 entries in a fixed order.
+VARIANTS = [(a, L, W, P) for a in ALGOS for L in LANE_BYTES for W in BLOCK_THREADS
+            for P in PLACEMENTS]
+DEFAULT_VARIANT = VARIANTS.index(("ac", 1024, 512, PLACE_LDS))
+
+FEATURES = ("log2_n", "log2_d", "m", "alphabet", "log2_states", "wm_mean_shift", "density")
+
+
+def variant_struct(k: int) -> Variant:
+    _, L, W, P = VARIANTS[k]
+    return Variant(L, W, P, 0, 0)
+
+
+@dataclass
+class PatternSetIndexes:
+    """Both indexes of one pattern set, uploaded."""
+    ac: Index
+    wm: Index
+    d: int
+    m: int
+
+    @classmethod
+    def build(cls, patterns, device="cuda"):
+        P = np.ascontiguousarray(patterns, np.uint8)
+        return cls(build_ac(P).upload(device), build_wm(P).upload(device), P.shape[0], P.shape[1])
+
+    def index(self, k: int) -> Index:
+        return self.ac if VARIANTS[k][0] == "ac" else self.wm
+
+    def lds_fits(self, k: int) -> bool:
+        """Whether variant k can run (LDS placement needs the tables to fit)."""
+        if VARIANTS[k][3] != PLACE_LDS:
+            return True
+        from . import workspace_bytes
+        try:
+            workspace_bytes(self.index(k), 1 << 20, variant_struct(k))
+            return True
+        except MpmError as e:
+            if e.status == MPM_EUNSUPPORTED:
+                return False
+            raise
+
+
+class Tuner:
+    """Times requests on all variants; keeps reusable device buffers."""
+
+    def __init__(self, device="cuda", target_bytes: int = 8 << 20, max_copies: int = 4096,
+                 reps: int = 3):
+        torch = _torch()
+        self.torch = torch
+        self.device = device
+        self.target_bytes = target_bytes
+        self.max_copies = max_copies
+        self.reps = reps
+        self.work = torch.empty(0, dtype=torch.uint8, device=device)
+        self.out = torch.empty((1, 2), dtype=torch.int32, device=device)
+        self.total = torch.zeros(1, dtype=torch.int64, device=device)
+        self._ws = {}
+
+    def _workspace(self, nbytes: int):
+        if self.work.numel() < nbytes:
+            self.work = self.torch.empty(max(nbytes, 2 * self.work.numel()), dtype=self.torch.uint8,
+                                         device=self.device)
+        return self.work
+
+    def count(self, sets: PatternSetIndexes, text, n: int | None = None) -> int:
+        """Number of matches (scan with output capacity 0)."""
+        from . import Scanner
+        n = text.numel() if n is None else n
+        key = id(sets)
+        sc = self._ws.get(key)
+        if sc is None or sc.ws.numel() * 8 < _ws_bytes(sets.ac, n):
+            sc = Scanner(sets.ac, max(n, 1 << 16), capacity=0, var=Variant(256, 256, 0, 0, 0))
+            self._ws[key] = sc
+        tot = C.c_uint64()
+        st = _L.mpm_scan_sync(sets.ac.handle, C.c_void_p(text.data_ptr()), n, None, 0,
+                              C.c_void_p(sc.ws.data_ptr()), sc.ws.numel() * 8,
+                              C.c_void_p(sc.total.data_ptr()), C.byref(sc.var), _stream_handle(),
+                              C.byref(tot))
+        if st not in (MPM_OK, -2):
+            _check(st, "count")
+        return int(tot.value)
+
+    def density(self, sets: PatternSetIndexes, text) -> float:
+        n = min(text.numel(), 1 << 16)
+        return self.count(sets, text[:n], n) / max(1, n)
+
+    def features(self, sets: PatternSetIndexes, text) -> np.ndarray:
+        ia, iw = sets.ac.info(), sets.wm.info()
+        n = text.numel()
+        return np.array([math.log2(max(n, 1)), math.log2(sets.d), sets.m, ia["n_classes"],
+                         math.log2(max(ia["n_states"], 1)), iw["wm_mean_shift"],
+                         self.density(sets, text)], np.float64)
+
+    def time_variant(self, sets: PatternSetIndexes, text, k: int, matches: int) -> float:
+        """Per-request milliseconds of variant k inside a batched launch."""
+        n = text.numel()
+        ix = sets.index(k)
+        v = variant_struct(k)
+        copies = int(min(self.max_copies, max(1, math.ceil(self.target_bytes / max(n, 1)))))
+        wb = int(_L.mpm_tune_work_bytes(ix.handle, n, copies, C.byref(v)))
+        if wb == 0:
+            return math.inf
+        work = self._workspace(wb + 256)
+        if self.out.shape[0] < max(1, matches):
+            self.out = self.torch.empty((max(1, matches), 2), dtype=self.torch.int32,
+                                        device=self.device)
+        ms = C.c_float()
+        base = (work.data_ptr() + 255) // 256 * 256
+        st = _L.mpm_tune_time(ix.handle, C.c_void_p(text.data_ptr()), n, copies, C.byref(v),
+                              C.c_void_p(self.out.data_ptr()), matches,
+                              C.c_void_p(self.total.data_ptr()), C.c_void_p(base),
+                              work.numel() - (base - work.data_ptr()), self.reps, _stream_handle(),
+                              C.byref(ms))
+        if st == MPM_EUNSUPPORTED:
+            return math.inf
+        _check(st, "mpm_tune_time")
+        return float(ms.value) / copies
+
+    def time_all(self, sets: PatternSetIndexes, text) -> np.ndarray:
+        """Per-request milliseconds of all 24 variants (inf where invalid)."""
+        matches = self.count(sets, text)
+        out = np.full(len(VARIANTS), math.inf)
+        for k in range(len(VARIANTS)):
+            if sets.lds_fits(k):
+                out[k] = self.time_variant(sets, text, k, matches)
+        return out
+
+
+def _ws_bytes(ix: Index, n: int) -> int:
+    from . import workspace_bytes
+    return workspace_bytes(ix, max(n, 1 << 16), Variant(256, 256, 0, 0, 0))
+
+
+def gbps(n: int, ms: np.ndarray) -> np.ndarray:
+    with np.errstate(divide="ignore"):
+        return np.where(np.isfinite(ms) & (ms > 0), n / (ms * 1e-3) / 1e9, 0.0)
+
+
+__all__ = ["VARIANTS", "DEFAULT_VARIANT", "FEATURES", "PatternSetIndexes", "Tuner", "gbps",
+           "variant_struct"]
