@@ -206,6 +206,11 @@ typedef struct {
     uint64_t capacity;
     uint64_t *d_total;
     mpm_variant variant;
+    /* Expected time of one of this request's chunks (any unit, 0 = unknown).
+     * Within a launch, requests sharing an index form a group; groups whose
+     * chunks take longest are queued first, so that long chunks do not end
+     * up as the launch's tail. Does not affect results. */
+    float cost_hint;
 } mpm_request;
 
 typedef struct mpm_batch mpm_batch;
@@ -243,8 +248,9 @@ void mpm_batch_free(mpm_batch *b);
 /* Time one request under one variant as it runs inside a batched launch:
  * the text is queued `copies` times in a single batched launch (every copy
  * writes the same output region and total, with identical values), the
- * launch runs once to warm up and then `reps` times, and *ms_out receives the
- * fastest launch in milliseconds (divide by copies for the per-request cost).
+ * launch runs once to warm up and then `reps` times back to back, and *ms_out
+ * receives the mean launch time in milliseconds (divide by copies for the
+ * per-request cost).
  * Not a step of the paper's method: it feeds the exhaustive autotuner that
  * picks each request's variant. d_work: device, 256-byte aligned, at least
  * mpm_tune_work_bytes; its contents are overwritten. Waits for the launches.

@@ -80,7 +80,7 @@ class Info(C.Structure):
 class Request(C.Structure):
     _fields_ = [("idx", C.c_void_p), ("d_text", C.c_void_p), ("n", C.c_uint64),
                 ("d_out", C.c_void_p), ("capacity", C.c_uint64), ("d_total", C.c_void_p),
-                ("variant", Variant)]
+                ("variant", Variant), ("cost_hint", C.c_float)]
 
 
 _vp, _u32, _u64 = C.c_void_p, C.c_uint32, C.c_uint64

@@ -41,7 +41,8 @@ class BatchScan:
     indexes[i], variants[i], capacities[i] belong to text i of the arena.
     """
 
-    def __init__(self, arena, offsets, lens, indexes, variants, capacities, device="cuda"):
+    def __init__(self, arena, offsets, lens, indexes, variants, capacities, device="cuda",
+                 cost_hints=None):
         torch = _torch()
         self.count = len(lens)
         self.lens = np.asarray(lens, np.int64)
@@ -67,6 +68,7 @@ class BatchScan:
             r.d_total = base_tot + 8 * i
             v = variants[i]
             r.variant = Variant(v.lane_bytes, v.block_threads, v.placement, v.grid, v.flags)
+            r.cost_hint = float(cost_hints[i]) if cost_hints is not None else 0.0
         h = C.c_void_p()
         _check(_L.mpm_batch_plan(reqs, self.count, C.byref(h)), "mpm_batch_plan")
         self._h = h

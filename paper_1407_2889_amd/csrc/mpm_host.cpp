@@ -661,8 +661,8 @@ mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n
     if (e != hipSuccess)
         return fail(MPM_EHIP, "mpm_scan_sync: %s", hipGetErrorString(e));
     if (hdr[WS_ERR]) {
-        hipMemsetAsync((uint8_t *)d_work + 4 * WS_ERR, 0, 4, s);
-        hipStreamSynchronize(s);
+        (void)hipMemsetAsync((uint8_t *)d_work + 4 * WS_ERR, 0, 4, s);
+        (void)hipStreamSynchronize(s);
         return fail(MPM_ESTATE, "mpm_scan_sync: device look-back did not complete");
     }
     if (*total > capacity)
@@ -698,6 +698,11 @@ struct mpm_batch {
     uint8_t *d_buf = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // Side streams (default priority) so that the plan's launches run as
+    // parallel branches: each launch's tail overlaps the others' work.
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> done;
+    hipEvent_t fork = nullptr;
 };
 
 extern "C" {
@@ -715,8 +720,16 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             const mpm_index *ix;
             LaunchCfg cfg;
             uint32_t kind;
+            float hint;
+            float group_hint;
         };
-        std::map<uint32_t, std::vector<Item>> byw;
+        // Launch key: block size and LDS class. A launch's LDS size is the
+        // largest its texts need, so texts with small tables are kept apart
+        // from texts whose tables limit a CU to one or two workgroups.
+        auto lds_class = [](uint32_t lds) -> uint32_t {
+            return lds <= 8192 ? 0 : lds <= 32768 ? 1 : lds <= 65536 ? 2 : 3;
+        };
+        std::map<std::pair<uint32_t, uint32_t>, std::vector<Item>> byw;
         for (uint32_t k = 0; k < count; k++) {
             const mpm_request &r = reqs[k];
             if (!r.idx || !r.d_total || (r.n && !r.d_text) || (r.capacity && !r.d_out)) {
@@ -740,6 +753,8 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             Item it;
             it.req = k;
             it.ix = r.idx;
+            it.hint = r.cost_hint > 0.f ? r.cost_hint : 0.f;
+            it.group_hint = 0.f;
             mpm_status st = resolve_variant(r.idx, &v, 0, &it.cfg);
             if (st) {
                 delete b;
@@ -751,19 +766,33 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return fail(MPM_EUNSUPPORTED, "mpm_batch_plan: too many copies of one pattern");
             }
             it.kind = batch_kind(r.idx, it.cfg);
-            byw[it.cfg.block_threads].push_back(it);
+            const auto key = std::make_pair(it.cfg.block_threads, lds_class(it.cfg.lds_bytes));
+            byw[key].push_back(it);
             if (r.variant.grid)
-                byw[it.cfg.block_threads].back().cfg.grid = r.variant.grid;
+                byw[key].back().cfg.grid = r.variant.grid;
         }
         for (auto &kv : byw) {
             std::vector<Item> &items = kv.second;
+            // Longest expected chunks first, by (index, kind) group so that
+            // consecutive chunks keep sharing their LDS tables.
+            std::map<std::pair<const mpm_index *, uint32_t>, float> ghint;
+            for (const Item &it : items) {
+                float &g = ghint[std::make_pair(it.ix, it.kind)];
+                g = std::max(g, it.hint);
+            }
+            for (Item &it : items)
+                it.group_hint = ghint[std::make_pair(it.ix, it.kind)];
             std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) {
+                if (x.group_hint != y.group_hint)
+                    return x.group_hint > y.group_hint;
                 if (x.ix != y.ix)
                     return (uintptr_t)x.ix < (uintptr_t)y.ix;
-                return x.kind < y.kind;
+                if (x.kind != y.kind)
+                    return x.kind < y.kind;
+                return x.hint > y.hint;
             });
             mpm_batch::Group g;
-            g.W = kv.first;
+            g.W = kv.first.first;
             std::map<const mpm_index *, uint32_t> slot;
             for (const Item &it : items) {
                 const mpm_request &r = reqs[it.req];
@@ -847,17 +876,50 @@ mpm_status mpm_batch_upload(mpm_batch *b, void *d_buf, uint64_t bytes, void *str
     return MPM_OK;
 }
 
-mpm_status mpm_batch_run(const mpm_batch *b, void *stream)
+static mpm_status ensure_side_streams(mpm_batch *b)
 {
+    const size_t need = b->groups.size() > 1 ? b->groups.size() : 0;
+    while (b->side.size() < need) {
+        hipStream_t s = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fail(MPM_EHIP, "mpm_batch: side stream creation failed");
+        b->side.push_back(s);
+        b->done.push_back(e);
+    }
+    if (need && !b->fork &&
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+        return fail(MPM_EHIP, "mpm_batch: event creation failed");
+    return MPM_OK;
+}
+
+mpm_status mpm_batch_run(const mpm_batch *cb, void *stream)
+{
+    mpm_batch *b = const_cast<mpm_batch *>(cb);
     if (!b || !b->d_buf)
         return fail(MPM_ESTATE, "mpm_batch_run: plan not uploaded");
+    mpm_status st0 = ensure_side_streams(b);
+    if (st0)
+        return st0;
     if (!b->zero_totals.empty()) {
         mpm_status st = launch_zero_totals((uint64_t *const *)(b->d_buf + b->zero_off),
                                            (uint32_t)b->zero_totals.size(), nullptr, stream);
         if (st)
             return st;
     }
-    for (const auto &g : b->groups) {
+    const bool fan = b->groups.size() > 1;
+    hipStream_t main_s = (hipStream_t)stream;
+    if (fan && hipEventRecord(b->fork, main_s) != hipSuccess)
+        return fail(MPM_EHIP, "mpm_batch_run: fork event failed");
+    for (size_t gi = 0; gi < b->groups.size(); gi++) {
+        const auto &g = b->groups[gi];
+        void *ls = stream;
+        if (fan) {
+            if (hipStreamWaitEvent(b->side[gi], b->fork, 0) != hipSuccess)
+                return fail(MPM_EHIP, "mpm_batch_run: stream wait failed");
+            ls = b->side[gi];
+        }
         BatchDev bd;
         memset(&bd, 0, sizeof bd);
         bd.texts = (const BatchText *)(b->d_buf + g.text_off);
@@ -866,9 +928,12 @@ mpm_status mpm_batch_run(const mpm_batch *b, void *stream)
         bd.ntiles = g.ntiles;
         bd.hdr = (uint32_t *)(b->d_buf + g.work_off);
         bd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
-        mpm_status st = launch_batch(bd, g.W, g.grid, g.lds, stream);
+        mpm_status st = launch_batch(bd, g.W, g.grid, g.lds, ls);
         if (st)
             return st;
+        if (fan && (hipEventRecord(b->done[gi], (hipStream_t)ls) != hipSuccess ||
+                    hipStreamWaitEvent(main_s, b->done[gi], 0) != hipSuccess))
+            return fail(MPM_EHIP, "mpm_batch_run: join failed");
     }
     return MPM_OK;
 }
@@ -878,12 +943,15 @@ mpm_status mpm_batch_capture(mpm_batch *b, void *stream)
     if (!b || !b->d_buf)
         return fail(MPM_ESTATE, "mpm_batch_capture: plan not uploaded");
     hipStream_t s = (hipStream_t)stream;
+    mpm_status st0 = ensure_side_streams(b);
+    if (st0)
+        return st0;
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -894,14 +962,14 @@ mpm_status mpm_batch_capture(mpm_batch *b, void *stream)
     e = hipStreamEndCapture(s, &g);
     if (st) {
         if (g)
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
         return st;
     }
     if (e != hipSuccess)
         return fail(MPM_EHIP, "mpm_batch_capture: end: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return fail(MPM_EHIP, "mpm_batch_capture: instantiate: %s", hipGetErrorString(e));
     }
     b->graph = g;
@@ -1008,23 +1076,20 @@ mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n
         hipEvent_t a, z;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&z) != hipSuccess)
             return fail(MPM_EHIP, "mpm_tune_time: event creation failed");
-        float best = 1e30f;
-        st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);  // warm-up
-        for (uint32_t r = 0; r < reps && st == MPM_OK; r++) {
-            (void)hipEventRecord(a, s);
+        // warm-up, then `reps` launches between two events: the mean launch
+        st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);
+        (void)hipEventRecord(a, s);
+        for (uint32_t r = 0; r < reps && st == MPM_OK; r++)
             st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);
-            (void)hipEventRecord(z, s);
-            if (st == MPM_OK && hipEventSynchronize(z) == hipSuccess) {
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, a, z);
-                best = std::min(best, ms);
-            }
-        }
+        (void)hipEventRecord(z, s);
+        float ms = 0.f;
+        if (st == MPM_OK && hipEventSynchronize(z) == hipSuccess)
+            (void)hipEventElapsedTime(&ms, a, z);
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(z);
         if (st)
             return st;
-        *ms_out = best;
+        *ms_out = ms / (float)reps;
         return MPM_OK;
     } catch (const std::bad_alloc &) {
         return fail(MPM_ENOMEM, "mpm_tune_time: out of host memory");
@@ -1036,9 +1101,15 @@ void mpm_batch_free(mpm_batch *b)
     if (!b)
         return;
     if (b->exec)
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : b->done)
+        (void)hipEventDestroy(e);
+    for (hipStream_t s : b->side)
+        (void)hipStreamDestroy(s);
+    if (b->fork)
+        (void)hipEventDestroy(b->fork);
     delete b;
 }
 

@@ -56,14 +56,14 @@ static DeviceLimits limits()
     static DeviceLimits cache[64];
     static bool have[64] = {false};
     int dev = 0;
-    hipGetDevice(&dev);
+    (void)hipGetDevice(&dev);
     std::lock_guard<std::mutex> g(mu);
     if (dev < 0 || dev >= 64)
         dev = 0;
     if (!have[dev]) {
         DeviceLimits L;
-        hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, dev);
-        hipDeviceGetAttribute(&L.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        (void)hipDeviceGetAttribute(&L.cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipDeviceGetAttribute(&L.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (L.cus <= 0)
             L.cus = 256;
         if (L.max_lds <= 0)
@@ -171,7 +171,7 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     if (ntiles) {
         const void *k = kernel_for(ix, *cfg);
         if (cfg->lds_bytes > 65536)
-            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg->lds_bytes);
+            (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cfg->lds_bytes);
         int nb = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)W, cfg->lds_bytes);
         if (e != hipSuccess || nb <= 0)
@@ -193,7 +193,7 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (c.lds_bytes > 65536)
-        hipFuncSetAttribute(kernel_for(ix, c), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute(kernel_for(ix, c), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)c.lds_bytes);
     if (ix->algo == MPM_ALGO_AC) {
         const AcDev a = ac_dev(ix);
@@ -225,7 +225,7 @@ uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t gr
     const DeviceLimits lim = limits();
     const void *k = batch_kernel_ptr(W);
     if (lds_bytes > 65536)
-        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     int nb = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (int)W, lds_bytes);
     if (e != hipSuccess || nb <= 0)
@@ -239,7 +239,7 @@ uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t gr
 mpm_status launch_batch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds, void *stream)
 {
     if (lds > 65536)
-        hipFuncSetAttribute(batch_kernel_ptr(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute(batch_kernel_ptr(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipError_t e = batch_launch(bd, W, grid, lds, (hipStream_t)stream);
     if (e != hipSuccess)
         return fail(MPM_EHIP, "batch launch: %s", hipGetErrorString(e));

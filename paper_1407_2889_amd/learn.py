@@ -1,13 +1,18 @@
 """Learned variant selector.
 
-A small dense network (7 -> 64 -> 64 -> 64 -> 24, ReLU) predicts, from a
-request's features, the standardised log-throughput of each of the 24 scan
-variants. It is trained on the exhaustive autotuner's timings with the
-library's own GPU kernels (forward, masked mean squared error, backward,
-Adam); this module only moves tensors and calls them. At selection time the
-variant with the highest prediction among those that can run is taken; when
-the predicted best beats the runner-up by less than ``margin`` (5% in
-throughput), the request falls back to the exhaustive autotuner.
+A small dense network (7 -> 64 -> 64 -> 64 -> 24, ReLU) maps a request's
+features to one standardised value per scan variant. It is trained on the
+exhaustive autotuner's timings with the library's own GPU kernels (forward,
+masked mean squared error, backward, Adam); this module only moves tensors
+and calls them.
+
+The selector holds two ensembles of such nets (different seeds, predictions
+averaged). The ranking ensemble predicts each variant's log slowdown against
+the request's fastest variant; the variant with the lowest prediction among
+those that can run is taken, and when the runner-up is predicted within
+``margin`` (5% in time) of it, the request falls back to the exhaustive
+autotuner. The timing ensemble predicts log milliseconds per request, which
+the batch planner uses to queue long requests first.
 """
 
 from __future__ import annotations
@@ -98,58 +103,107 @@ class Net:
         return hist
 
 
-class Selector:
-    """Feature / target normalisation around a trained Net."""
+class _Ensemble:
+    """Nets trained on the same standardised data from different seeds; their
+    predictions are averaged."""
 
-    def __init__(self, net: Net, x_mean, x_std, y_mean, y_std):
-        self.net = net
+    def __init__(self, nets, x_mean, x_std, y_mean, y_std):
+        self.nets = nets
         self.x_mean, self.x_std = np.asarray(x_mean), np.asarray(x_std)
         self.y_mean, self.y_std = float(y_mean), float(y_std)
 
     @classmethod
-    def fit(cls, feats: np.ndarray, gbs: np.ndarray, steps: int = 3000, lr: float = 2e-3,
-            seed: int = 0, device="cuda"):
-        """feats [R, 7]; gbs [R, 24] measured GB/s (0 where a variant cannot run)."""
+    def fit(cls, feats, target, valid, n_nets, steps, lr, seed, device):
         torch = _torch()
-        valid = gbs > 0
-        logy = np.where(valid, np.log(np.maximum(gbs, 1e-12)), 0.0)
         x_mean = feats.mean(0)
         x_std = feats.std(0) + 1e-6
-        y_mean = float(logy[valid].mean())
-        y_std = float(logy[valid].std() + 1e-6)
+        y_mean = float(target[valid].mean())
+        y_std = float(target[valid].std() + 1e-6)
         X = torch.from_numpy(((feats - x_mean) / x_std).astype(np.float32)).to(device)
-        T = torch.from_numpy(((logy - y_mean) / y_std * valid).astype(np.float32)).to(device)
+        T = torch.from_numpy((np.where(valid, (target - y_mean) / y_std, 0.0)).astype(np.float32)).to(device)
         M = torch.from_numpy(valid.astype(np.float32)).to(device)
-        net = Net(seed=seed, device=device)
-        hist = net.train(X, T, M, steps, lr, log_every=max(1, steps // 10))
-        sel = cls(net, x_mean, x_std, y_mean, y_std)
-        sel.history = hist
-        return sel
+        nets, hist = [], []
+        for k in range(n_nets):
+            net = Net(seed=seed + k, device=device)
+            hist.append(net.train(X, T, M, steps, lr, log_every=max(1, steps // 4)))
+            nets.append(net)
+        ens = cls(nets, x_mean, x_std, y_mean, y_std)
+        ens.history = hist
+        return ens
 
-    def predict_gbps(self, feats: np.ndarray) -> np.ndarray:
+    def predict(self, feats):
         torch = _torch()
         X = torch.from_numpy(((np.atleast_2d(feats) - self.x_mean) / self.x_std)
-                             .astype(np.float32)).to(self.net.device)
-        y = self.net.forward(X).cpu().numpy().astype(np.float64)
-        return np.exp(y * self.y_std + self.y_mean)
+                             .astype(np.float32)).to(self.nets[0].device)
+        ys = [net.forward(X).cpu().numpy().astype(np.float64) for net in self.nets]
+        return np.mean(ys, axis=0) * self.y_std + self.y_mean
+
+    def state(self, prefix):
+        d = {f"{prefix}_x_mean": self.x_mean, f"{prefix}_x_std": self.x_std,
+             f"{prefix}_y": np.array([self.y_mean, self.y_std])}
+        for k, net in enumerate(self.nets):
+            d[f"{prefix}_theta{k}"] = net.theta.cpu().numpy()
+        return d
+
+    @classmethod
+    def from_state(cls, z, prefix, device):
+        nets = []
+        k = 0
+        while f"{prefix}_theta{k}" in z:
+            nets.append(Net(theta=z[f"{prefix}_theta{k}"], device=device))
+            k += 1
+        y = z[f"{prefix}_y"]
+        return cls(nets, z[f"{prefix}_x_mean"], z[f"{prefix}_x_std"], float(y[0]), float(y[1]))
+
+
+class Selector:
+    """Two ensembles over the request features: `rank` predicts each variant's
+    log slowdown relative to the request's fastest variant (what the choice
+    needs), `time` predicts each variant's log milliseconds per request (what
+    the batch planner's queue order needs)."""
+
+    def __init__(self, rank: _Ensemble, timing: _Ensemble):
+        self.rank = rank
+        self.timing = timing
+
+    @classmethod
+    def fit(cls, feats: np.ndarray, ms: np.ndarray, n_nets: int = 5, steps: int = 2000,
+            lr: float = 2e-3, seed: int = 0, device="cuda"):
+        """feats [R, 7]; ms [R, 24] per-request milliseconds (inf where a
+        variant cannot run)."""
+        valid = np.isfinite(ms) & (ms > 0)
+        safe = np.where(valid, ms, 1.0)
+        rel = np.log(safe / np.min(np.where(valid, ms, np.inf), axis=1, keepdims=True))
+        rank = _Ensemble.fit(feats, np.where(valid, rel, 0.0), valid, n_nets, steps, lr, seed, device)
+        timing = _Ensemble.fit(feats, np.log(safe), valid, max(1, n_nets // 2), steps, lr,
+                               seed + 100, device)
+        sel = cls(rank, timing)
+        sel.history = {"rank": rank.history, "time": timing.history}
+        return sel
+
+    def predict_ms(self, feats: np.ndarray) -> np.ndarray:
+        return np.exp(self.timing.predict(feats))
+
+    def predict_gbps(self, feats: np.ndarray, n: np.ndarray) -> np.ndarray:
+        return np.asarray(n, np.float64)[:, None] / (self.predict_ms(feats) * 1e-3) / 1e9
 
     def choose(self, feats: np.ndarray, valid: np.ndarray, margin: float = 0.05):
-        """Per request: (variant, needs_fallback). valid [R, 24] booleans."""
-        pred = self.predict_gbps(feats)
-        pred = np.where(valid, pred, -np.inf)
-        order = np.argsort(-pred, axis=1)
+        """Per request: (variant, needs_fallback). The predicted best must beat
+        the predicted runner-up by `margin` (relative time) or the request
+        falls back to the exhaustive autotuner."""
+        score = np.where(valid, self.rank.predict(feats), np.inf)
+        order = np.argsort(score, axis=1)
+        r = np.arange(len(order))
         best = order[:, 0]
-        top = pred[np.arange(len(best)), best]
-        second = pred[np.arange(len(best)), order[:, 1]]
-        fallback = (top - second) / np.maximum(top, 1e-30) < margin
-        return best, fallback
+        gap = np.exp(score[r, order[:, 1]] - score[r, best]) - 1.0
+        return best, gap < margin
 
     def save(self, path: str):
-        np.savez(path, theta=self.net.theta.cpu().numpy(), x_mean=self.x_mean, x_std=self.x_std,
-                 y_mean=self.y_mean, y_std=self.y_std)
+        d = self.rank.state("rank")
+        d.update(self.timing.state("time"))
+        np.savez(path, **d)
 
     @classmethod
     def load(cls, path: str, device="cuda"):
         z = np.load(path)
-        return cls(Net(theta=z["theta"], device=device), z["x_mean"], z["x_std"],
-                   float(z["y_mean"]), float(z["y_std"]))
+        return cls(_Ensemble.from_state(z, "rank", device), _Ensemble.from_state(z, "time", device))

@@ -1,0 +1,177 @@
+"""Variant selection for batched scans: timing database, selector training and
+the comparison of selection policies on a batch.
+
+Policies compared on one batch (each runs the whole batch as one replayed
+HIP graph, every text under the variant the policy picked):
+  exhaustive - every request timed on all 24 variants, fastest kept;
+  learned    - the selector's choice, except where its predicted best beats
+               the runner-up by less than the margin: those requests take
+               the exhaustive choice (the fallback);
+  default    - one fixed variant for every request.
+Regret of the learned policy = 1 - (its batch GB/s) / (exhaustive GB/s).
+"""
+
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+import synth
+
+from . import batch as _batch
+from . import tune
+from .learn import Selector
+
+
+def training_requests(n_req: int, n_sets: int, seed: int, stream_bytes: int = 256 << 20,
+                      max_len: int = 4 << 20, d_hi: int = 50000):
+    """Seeded requests for the timing database: text slices of one EST-shaped
+    stream (256-byte aligned starts) paired with a pool of pattern sets."""
+    lens, ds, ms = synth.batch_request_shapes(n_req, n_sets, seed, seed + 1, max_len=max_len,
+                                              d_hi=d_hi)
+    stream = synth.est_text(stream_bytes, seed=seed + 2)
+    rng = np.random.default_rng(seed + 3)
+    offs = (rng.integers(0, stream_bytes - lens + 1) // 256 * 256).astype(np.int64)
+    pair = rng.integers(0, n_sets, n_req)
+    sets = []
+    for k in range(n_sets):
+        d = int(ds[k])
+        sets.append(synth.pattern_set(stream, d=d, m=int(ms[k]), n_planted=d // 10,
+                                      seed=seed + 100 + k))
+    return stream, sets, list(zip(pair.tolist(), offs.tolist(), lens.tolist()))
+
+
+def build_db(tuner: tune.Tuner, sets_idx, stream_dev, reqs, log=None):
+    """Features [R, 7] and per-request milliseconds [R, 24] of every request."""
+    R = len(reqs)
+    feats = np.zeros((R, 7))
+    ms = np.full((R, len(tune.VARIANTS)), np.inf)
+    t0 = time.perf_counter()
+    for i, (p, off, n) in enumerate(reqs):
+        text = stream_dev[off:off + n]
+        feats[i] = tuner.features(sets_idx[p], text)
+        ms[i] = tuner.time_all(sets_idx[p], text)
+        if log and (i + 1) % max(1, R // 10) == 0:
+            log(f"[tune] {i + 1}/{R} requests timed ({time.perf_counter() - t0:.1f}s)")
+    return feats, ms
+
+
+def to_gbps(lens: np.ndarray, ms: np.ndarray) -> np.ndarray:
+    return np.stack([tune.gbps(int(n), ms[i]) for i, n in enumerate(lens)])
+
+
+def best_uniform_variant(ms: np.ndarray) -> int:
+    """The single variant with the least total time over a timing database
+    (requests whose tables do not fit in LDS take its global-placement twin):
+    the fixed choice a batch would use without the selector."""
+    best, best_t = 0, math.inf
+    for k in range(len(tune.VARIANTS)):
+        pk = np.array([uniform_choice(k, np.isfinite(ms[i])) for i in range(len(ms))])
+        t = float(ms[np.arange(len(ms)), pk].sum())
+        if t < best_t:
+            best, best_t = k, t
+    return best
+
+
+def uniform_choice(k: int, valid_row: np.ndarray) -> int:
+    if valid_row[k]:
+        return k
+    a, L, W, _ = tune.VARIANTS[k]
+    return tune.VARIANTS.index((a, L, W, tune.PLACEMENTS[1]))
+
+
+def evaluate(b: synth.Batch, tuner: tune.Tuner, selector: Selector, default_variant: int,
+             margin: float = 0.05, reps: int = 5, log=None):
+    """Run the three policies on batch b; returns a result dict."""
+    import torch
+    sets_idx = [tune.PatternSetIndexes.build(ps.patterns) for ps in b.sets]
+    arena, offs, lens = _batch.pack_texts(b.texts)
+    R = len(b.texts)
+    texts = [arena[int(offs[i]):int(offs[i]) + int(lens[i])] for i in range(R)]
+    pset = [sets_idx[int(b.pairing[i])] for i in range(R)]
+    valid = np.array([[s.lds_fits(k) for k in range(len(tune.VARIANTS))] for s in sets_idx])
+    valid_r = valid[b.pairing.astype(int)]
+
+    t0 = time.perf_counter()
+    feats = np.stack([tuner.features(pset[i], texts[i]) for i in range(R)])
+    t_feat = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    learned, fallback = selector.choose(feats, valid_r, margin)
+    ms_pred = selector.predict_ms(feats)
+    t_infer = time.perf_counter() - t0
+
+    # exhaustive autotuning of every request (the reference, and the source of
+    # the fallback choices)
+    t0 = time.perf_counter()
+    ms = np.stack([tuner.time_all(pset[i], texts[i]) for i in range(R)])
+    t_exh = time.perf_counter() - t0
+    exh = np.argmin(ms, axis=1)
+    t_fallback = t_exh * float(fallback.mean())
+    final = np.where(fallback, exh, learned)
+    default = np.array([uniform_choice(default_variant, valid_r[i]) for i in range(R)])
+    caps = [tuner.count(pset[i], texts[i]) for i in range(R)]
+    if log:
+        log(f"[select] features {t_feat:.2f}s, inference {t_infer * 1e3:.1f}ms, exhaustive "
+            f"{t_exh:.1f}s, fallback rate {fallback.mean():.3f}")
+
+    # Queue hints: each policy only uses what it knows. Exhaustive: measured
+    # times; learned: predicted times (measured ones where it fell back);
+    # default: none.
+    ms_learned = np.where(fallback[:, None], ms, ms_pred)
+
+    def run(choice, ms_known):
+        idx = [pset[i].index(int(choice[i])) for i in range(R)]
+        var = [tune.variant_struct(int(choice[i])) for i in range(R)]
+        hint = None
+        if ms_known is not None:
+            hint = [tune.chunk_cost_hint(int(choice[i]), float(ms_known[i, int(choice[i])]),
+                                         int(lens[i]), pset[i].m) for i in range(R)]
+        bs = _batch.BatchScan(arena, offs, lens, idx, var, caps, cost_hints=hint)
+        bs.capture()
+        bs.replay()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, z in ev:
+            a.record()
+            bs.replay()
+            z.record()
+        torch.cuda.synchronize()
+        tms = float(np.median([a.elapsed_time(z) for a, z in ev]))
+        tot = bs.totals_host()
+        return tms, tot, bs.groups
+
+    total_bytes = int(np.sum(lens))
+    res = {"requests": R, "text_bytes": total_bytes}
+    totals = {}
+    for name, choice, known in (("exhaustive", exh, ms), ("learned", final, ms_learned),
+                                ("default", default, None)):
+        tms, tot, groups = run(choice, known)
+        res[f"{name}_ms"] = tms
+        res[f"{name}_gbps"] = total_bytes / (tms * 1e-3) / 1e9
+        res[f"{name}_launches"] = groups
+        totals[name] = tot
+    res["totals_agree"] = bool(all(np.array_equal(totals["exhaustive"], t) for t in totals.values())
+                               and np.array_equal(totals["exhaustive"], np.array(caps)))
+    res["regret"] = 1.0 - res["learned_gbps"] / res["exhaustive_gbps"]
+    res["gain_over_default"] = res["learned_gbps"] / res["default_gbps"] - 1.0
+    res["fallback_rate"] = float(fallback.mean())
+    res["selection_overhead_s"] = {"features": t_feat, "inference": t_infer,
+                                   "fallback_tuning": t_fallback, "exhaustive_tuning": t_exh}
+    # how often the learned pick (before fallback) equals the exhaustive best,
+    # and its predicted-vs-isolated slowdown on the picks that differ
+    iso = to_gbps(np.asarray(lens), ms)
+    best = iso[np.arange(R), exh]
+    res["pick_agreement"] = float(np.mean(learned == exh))
+    res["isolated_regret_learned_only"] = float(
+        1.0 - iso[np.arange(R), learned].sum() / max(best.sum(), 1e-30))
+    tbest = ms[np.arange(R), exh].sum()
+    res["time_regret_isolated"] = {
+        "learned_no_fallback": float(ms[np.arange(R), learned].sum() / tbest - 1),
+        "learned": float(ms[np.arange(R), final].sum() / tbest - 1),
+        "default": float(ms[np.arange(R), default].sum() / tbest - 1)}
+    res["default_variant"] = list(tune.VARIANTS[default_variant])
+    res["matches"] = int(np.sum(caps))
+    return res

@@ -79,12 +79,13 @@ class PatternSetIndexes:
 class Tuner:
     """Times requests on all variants; keeps reusable device buffers."""
 
-    def __init__(self, device="cuda", target_bytes: int = 8 << 20, max_copies: int = 4096,
-                 reps: int = 3):
+    def __init__(self, device="cuda", target_chunks: int = 2048, max_bytes: int = 32 << 20,
+                 max_copies: int = 4096, reps: int = 3):
         torch = _torch()
         self.torch = torch
         self.device = device
-        self.target_bytes = target_bytes
+        self.target_chunks = target_chunks
+        self.max_bytes = max_bytes
         self.max_copies = max_copies
         self.reps = reps
         self.work = torch.empty(0, dtype=torch.uint8, device=device)
@@ -127,12 +128,19 @@ class Tuner:
                          math.log2(max(ia["n_states"], 1)), iw["wm_mean_shift"],
                          self.density(sets, text)], np.float64)
 
-    def time_variant(self, sets: PatternSetIndexes, text, k: int, matches: int) -> float:
+    def time_variant(self, sets: PatternSetIndexes, text, k: int, matches: int,
+                     reps: int | None = None) -> float:
         """Per-request milliseconds of variant k inside a batched launch."""
         n = text.numel()
         ix = sets.index(k)
         v = variant_struct(k)
-        copies = int(min(self.max_copies, max(1, math.ceil(self.target_bytes / max(n, 1)))))
+        # enough copies to keep every workgroup busy (steady-state cost per
+        # request, which is what a request adds to a large batch), within a
+        # byte budget per timing launch
+        _, L, W, _ = VARIANTS[k]
+        chunks = max(1, math.ceil(max(n - sets.m + 1, 1) / (L * W)))
+        copies = math.ceil(self.target_chunks / chunks)
+        copies = int(max(1, min(copies, self.max_copies, self.max_bytes // max(n, 1))))
         wb = int(_L.mpm_tune_work_bytes(ix.handle, n, copies, C.byref(v)))
         if wb == 0:
             return math.inf
@@ -145,26 +153,43 @@ class Tuner:
         st = _L.mpm_tune_time(ix.handle, C.c_void_p(text.data_ptr()), n, copies, C.byref(v),
                               C.c_void_p(self.out.data_ptr()), matches,
                               C.c_void_p(self.total.data_ptr()), C.c_void_p(base),
-                              work.numel() - (base - work.data_ptr()), self.reps, _stream_handle(),
+                              work.numel() - (base - work.data_ptr()), reps or self.reps,
+                              _stream_handle(),
                               C.byref(ms))
         if st == MPM_EUNSUPPORTED:
             return math.inf
         _check(st, "mpm_tune_time")
         return float(ms.value) / copies
 
-    def time_all(self, sets: PatternSetIndexes, text) -> np.ndarray:
-        """Per-request milliseconds of all 24 variants (inf where invalid)."""
+    def time_all(self, sets: PatternSetIndexes, text, refine: int = 4) -> np.ndarray:
+        """Per-request milliseconds of all 24 variants (inf where invalid):
+        every runnable variant once, then the `refine` fastest again with
+        more repetitions (their times replace the first ones)."""
         matches = self.count(sets, text)
         out = np.full(len(VARIANTS), math.inf)
         for k in range(len(VARIANTS)):
             if sets.lds_fits(k):
-                out[k] = self.time_variant(sets, text, k, matches)
+                out[k] = self.time_variant(sets, text, k, matches, reps=1)
+        for k in np.argsort(out)[:refine]:
+            if np.isfinite(out[k]):
+                out[k] = self.time_variant(sets, text, int(k), matches)
         return out
 
 
 def _ws_bytes(ix: Index, n: int) -> int:
     from . import workspace_bytes
     return workspace_bytes(ix, max(n, 1 << 16), Variant(256, 256, 0, 0, 0))
+
+
+def chunk_cost_hint(k: int, ms_per_request: float, n: int, m: int) -> float:
+    """Expected duration of one chunk of a request under variant k (its
+    steady-state time per starting position times the positions per
+    chunk): the batch planner queues long chunks first."""
+    _, L, W, _ = VARIANTS[k]
+    starts = max(n - m + 1, 1)
+    if not np.isfinite(ms_per_request):
+        return 0.0
+    return float(ms_per_request / starts * min(starts, L * W) * 1e3)
 
 
 def gbps(n: int, ms: np.ndarray) -> np.ndarray:

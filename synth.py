@@ -49,15 +49,15 @@ def est_text(n: int, seed: int, mean_len: float = 500.0, sigma: float = 0.5,
     """EST-shaped DNA text (uint8[n]): log-normal records, 1% N, newline separators."""
     rng = np.random.default_rng(seed)
     out = np.empty(n, dtype=np.uint8)
-    p_base = (1.0 - p_n) / 4.0
-    # cumulative thresholds for A, C, G, T; anything above is N
-    thr = np.array([p_base, 2 * p_base, 3 * p_base, 4 * p_base], dtype=np.float32)
+    # byte = LUT[uniform integer in [0, 400)]: 99/400 = 0.2475 for each base,
+    # 4/400 = 0.01 for N (p_n is fixed at 0.01 by this table)
+    assert abs(p_n - 0.01) < 1e-12, "the lookup table encodes 1% N"
+    lut = np.empty(400, dtype=np.uint8)
+    lut[0:99], lut[99:198], lut[198:297], lut[297:396], lut[396:400] = ACGTN
     step = 64 * MiB
     for lo in range(0, n, step):
         hi = min(n, lo + step)
-        u = rng.random(hi - lo, dtype=np.float32)
-        code = np.searchsorted(thr, u, side="right").astype(np.uint8)  # 0..4
-        out[lo:hi] = ACGTN[code]
+        out[lo:hi] = lut[rng.integers(0, 400, hi - lo, dtype=np.uint16)]
     mu = math.log(mean_len) - 0.5 * sigma * sigma
     # record lengths until the text is covered; '\n' follows each record
     pos = 0
