@@ -27,6 +27,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_1407_2889_amd.build` "
         "(there is no CPU fallback)")
 
+# torch first: it ships its own HIP runtime under the same soname as the one
+# libmpm.so was linked against. Loaded in this order, libmpm binds to torch's
+# copy; loaded the other way round, the process holds two HIP runtimes and the
+# one libmpm uses finds no device.
+import torch  # noqa: E402,F401
+
 _L = C.CDLL(LIB_PATH)
 
 MPM_OK, MPM_EINVAL, MPM_EOVERFLOW, MPM_ENOMEM, MPM_EHIP, MPM_ETOOBIG, MPM_EUNSUPPORTED, MPM_ESTATE = (

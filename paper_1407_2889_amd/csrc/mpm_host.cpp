@@ -250,7 +250,17 @@ static mpm_status build_ac_tables(mpm_index *ix)
                     ix->perm_byte[k] = ix->class_bytes[owner[k]];
                     ix->perm_col[k] = (uint8_t)((owner[k] + 1) * ix->state_bytes);
                 } else {
+                    // A code of no pattern byte goes to column 0 whatever the
+                    // byte; its expected byte only decides whether the kernel
+                    // can skip the exact per-byte test, so pick a likely
+                    // separator byte with this code when there is one.
+                    static const uint8_t likely[] = {'\n', 'N', '\r', ' ', 'n', '>', '\t', '-', 0};
                     ix->perm_byte[k] = (uint8_t)(((k + 1) & 7) << sh);  // has another code
+                    for (uint8_t b : likely)
+                        if (((b >> sh) & 7) == (uint32_t)k && !present[b]) {
+                            ix->perm_byte[k] = b;
+                            break;
+                        }
                     ix->perm_col[k] = 0;
                 }
             }
@@ -663,6 +673,8 @@ mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n
     if (hdr[WS_ERR]) {
         (void)hipMemsetAsync((uint8_t *)d_work + 4 * WS_ERR, 0, 4, s);
         (void)hipStreamSynchronize(s);
+        if (hdr[WS_ERR] & WS_ERR_LDS_LAYOUT)
+            return fail(MPM_ESTATE, "mpm_scan_sync: kernel LDS layout check failed");
         return fail(MPM_ESTATE, "mpm_scan_sync: device look-back did not complete");
     }
     if (*total > capacity)

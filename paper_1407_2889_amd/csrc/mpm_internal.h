@@ -80,6 +80,8 @@ struct TextDesc {
 // counter, launch epoch, device error flag. Followed (at byte 64) by one
 // uint64 look-back status word per tile.
 enum { WS_TICKET = 0, WS_DONE = 1, WS_EPOCH = 2, WS_ERR = 3 };
+// Device error flag bits.
+enum { WS_ERR_LOOKBACK = 1u, WS_ERR_LDS_LAYOUT = 2u };
 static const uint64_t WS_HEADER_BYTES = 64;
 
 struct ScanDev {

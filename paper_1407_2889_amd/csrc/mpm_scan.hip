@@ -130,8 +130,6 @@ static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
     return wm_kernel(c);
 }
 
-static const uint32_t STATIC_LDS_RESERVE = 512;
-
 uint64_t tile_bytes(const LaunchCfg &cfg)
 {
     return (uint64_t)cfg.lane_bytes * cfg.block_threads * cfg.ilp;
@@ -152,9 +150,11 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     if (d.placement > MPM_PLACE_GLOBAL)
         return fail(MPM_EINVAL, "variant: unknown placement %u", d.placement);
     const DeviceLimits lim = limits();
-    const uint32_t fixed = ix->algo == MPM_ALGO_AC ? 512u : 0u;  // AC byte-class map
+    // dynamic LDS: the kernels' fixed header and byte-class regions, then the
+    // tables when they are placed in LDS
+    const uint32_t fixed = 1024u;
     const uint64_t table_lds = fixed + ix->table_bytes;
-    const bool fits = table_lds + STATIC_LDS_RESERVE <= (uint64_t)lim.max_lds;
+    const bool fits = table_lds <= (uint64_t)lim.max_lds;
     uint32_t place = d.placement;
     if (place == MPM_PLACE_AUTO)
         place = fits ? MPM_PLACE_LDS : MPM_PLACE_GLOBAL;

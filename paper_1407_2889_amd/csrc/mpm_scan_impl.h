@@ -50,6 +50,53 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte load/store
 template <typename T> struct TabPtr<true, T> { using type = lds_cptr<T>; };
 
 static const int K_SLOTS = 4;  // occurrences a lane keeps in registers
+
+// Dynamic LDS layout. The scan kernels declare no static LDS, so their
+// dynamic allocation starts at LDS address 0 (checked at kernel start) and
+// every region sits at a constant address: table reads then need no base
+// register, the constant goes into the ds_read offset field.
+static const uint32_t LDS_HDR_OFF = 0;     // LdsHdr: per-workgroup scalars
+static const uint32_t LDS_CLS_OFF = 512;   // AC: column byte offset per byte value
+static const uint32_t LDS_TAB_OFF = 1024;  // matching tables (LDS placement)
+
+template <typename T>
+__device__ __forceinline__ LDS_AS T *lds_at(uint32_t off)
+{
+    return (LDS_AS T *)(uintptr_t)off;
+}
+
+static const int LDS_SCAN_WORDS = 2 * (1024 / 64) + 1;  // chunk_offsets words, at most
+
+struct LdsHdr {
+    uint64_t scan[LDS_SCAN_WORDS];
+    uint64_t tile;   // chunk ticket of the workgroup's current chunk
+    uint32_t epoch;  // launch epoch
+    uint32_t pad;
+    TextDesc td;     // the current chunk's text (single-index kernel)
+    BatchText bt;    // the current chunk's text (batched kernel)
+};
+static_assert(sizeof(LdsHdr) <= LDS_CLS_OFF - LDS_HDR_OFF, "LDS header overflows its region");
+
+// Whether the kernel's dynamic LDS starts at address 0. If not (static LDS
+// appeared in the kernel), flag a device error and let every workgroup return
+// before taking a ticket, so the workspace stays clean.
+__device__ __forceinline__ bool lds_layout_ok(uint8_t *smem, uint32_t *hdr)
+{
+    if ((uint32_t)(uintptr_t)(LDS_AS uint8_t *)smem == 0u)
+        return true;
+    if (threadIdx.x == 0)
+        atomicOr(&hdr[WS_ERR], WS_ERR_LDS_LAYOUT);
+    return false;
+}
+
+// A uniform value kept in a VGPR (v_perm takes at most one SGPR operand, so
+// its table words are held in VGPRs once instead of being copied per use).
+__device__ __forceinline__ uint32_t in_vgpr(uint32_t x)
+{
+    uint32_t r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
 static const uint32_t SPIN_LIMIT = 1u << 24;
 
 // ---------------------------------------------------------------------------
@@ -111,7 +158,7 @@ __device__ __forceinline__ uint64_t look_back(uint64_t *status, uint64_t g, uint
         if ((ready & need) != need) {
             if (++spins > SPIN_LIMIT) {  // never expected; keeps every wave finite
                 if (lane == 0)
-                    atomicOr(err, 1u);
+                    atomicOr(err, (uint32_t)WS_ERR_LOOKBACK);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -208,11 +255,21 @@ __device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_
 
 // Cooperative global -> LDS copy (bytes multiple of 16, both 16-aligned).
 template <int W>
-__device__ __forceinline__ void copy_to_lds(uint8_t *dst, const uint8_t *src, uint32_t bytes)
+__device__ __forceinline__ void copy_to_lds(uint32_t dst, const uint8_t *src, uint32_t bytes)
 {
     glb_cptr<v4u> s = (glb_cptr<v4u>)src;
-    LDS_AS v4u *d = (LDS_AS v4u *)dst;
-    for (uint32_t k = threadIdx.x; k < bytes / 16; k += W)
+    LDS_AS v4u *d = lds_at<v4u>(dst);
+    const uint32_t n = bytes / 16;
+    uint32_t k = threadIdx.x;
+    // four loads in flight per thread before their stores
+    for (; k + 3 * W < n; k += 4 * W) {
+        const v4u a = s[k], b = s[k + W], c = s[k + 2 * W], e = s[k + 3 * W];
+        d[k] = a;
+        d[k + W] = b;
+        d[k + 2 * W] = c;
+        d[k + 3 * W] = e;
+    }
+    for (; k < n; k += W)
         d[k] = s[k];
 }
 
@@ -302,7 +359,7 @@ __device__ __forceinline__ uint32_t swar_cols(uint32_t w, uint32_t sh, uint32_t 
     const uint32_t col = __builtin_amdgcn_perm(pc_hi, pc_lo, code);
     const uint32_t x = w ^ expect;
     const uint32_t nz = (((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;  // bit 7: byte != 0
-    return col & ~((nz >> 7) * 0xFFu);
+    return col & ~(nz | (nz - (nz >> 7)));  // 0xFF in every byte != 0
 }
 
 template <typename St, bool InLds, bool Swar, int Ilp>
@@ -315,33 +372,40 @@ struct AcWalk {
 
     // Copy what this walker reads from LDS (no barrier).
     template <int W>
-    __device__ __forceinline__ static void load(const AcDev &a, uint8_t *smem)
+    __device__ __forceinline__ static void load(const AcDev &a)
     {
-        copy_to_lds<W>(smem, a.cls, 512);
+        copy_to_lds<W>(LDS_CLS_OFF, a.cls, 512);
         if (InLds)
-            copy_to_lds<W>(smem + 512, (const uint8_t *)a.dfa, a.dfa_bytes);
+            copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.dfa_bytes);
     }
 
-    __device__ __forceinline__ void bind(const AcDev &a, uint8_t *smem)
+    __device__ __forceinline__ void bind(const AcDev &a)
     {
         rowb = a.cp * (uint32_t)sizeof(St);
         first_term = a.first_term;
         m = a.m;
         sh = a.swar_shift;
-        pb_lo = a.perm_byte_lo;
         pb_hi = a.perm_byte_hi;
-        pc_lo = a.perm_col_lo;
         pc_hi = a.perm_col_hi;
-        cls = (lds_cptr<uint16_t>)smem;
-        dfab = InLds ? (typename TabPtr<InLds, uint8_t>::type)(smem + 512)
-                     : (typename TabPtr<InLds, uint8_t>::type)a.dfa;
+        if (Swar) {
+            pb_lo = in_vgpr(a.perm_byte_lo);
+            pc_lo = in_vgpr(a.perm_col_lo);
+        } else {
+            pb_lo = a.perm_byte_lo;
+            pc_lo = a.perm_col_lo;
+        }
+        cls = lds_at<const uint16_t>(LDS_CLS_OFF);
+        if constexpr (InLds)
+            dfab = lds_at<const uint8_t>(LDS_TAB_OFF);
+        else
+            dfab = (glb_cptr<uint8_t>)a.dfa;
     }
 
     template <int W>
-    __device__ __forceinline__ void setup(const AcDev &a, uint8_t *smem, uint32_t /*unused*/)
+    __device__ __forceinline__ void setup(const AcDev &a, uint32_t /*unused*/)
     {
-        load<W>(a, smem);
-        bind(a, smem);
+        load<W>(a);
+        bind(a);
         __syncthreads();
     }
 
@@ -352,14 +416,31 @@ struct AcWalk {
         return *(typename TabPtr<InLds, St>::type)(dfab + off);
     }
 
-    // Byte-offset columns of the 16 bytes of c.
+    // Byte-offset columns of the 16 bytes of c. Swar: when every byte is its
+    // code's expected byte (the usual case: the expected byte of a code is
+    // its pattern byte, or for codes of no pattern byte a likely separator),
+    // the columns are one v_perm per word; otherwise the exact per-byte test
+    // sends unexpected bytes to column 0.
     __device__ __forceinline__ void cols16(const v4u c, uint32_t (&cw)[4]) const
     {
         if (Swar) {
-            cw[0] = swar_cols(c.x, sh, pb_lo, pb_hi, pc_lo, pc_hi);
-            cw[1] = swar_cols(c.y, sh, pb_lo, pb_hi, pc_lo, pc_hi);
-            cw[2] = swar_cols(c.z, sh, pb_lo, pb_hi, pc_lo, pc_hi);
-            cw[3] = swar_cols(c.w, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+            const uint32_t k0 = (c.x >> sh) & 0x07070707u, k1 = (c.y >> sh) & 0x07070707u;
+            const uint32_t k2 = (c.z >> sh) & 0x07070707u, k3 = (c.w >> sh) & 0x07070707u;
+            const uint32_t miss = (c.x ^ __builtin_amdgcn_perm(pb_hi, pb_lo, k0)) |
+                                  (c.y ^ __builtin_amdgcn_perm(pb_hi, pb_lo, k1)) |
+                                  (c.z ^ __builtin_amdgcn_perm(pb_hi, pb_lo, k2)) |
+                                  (c.w ^ __builtin_amdgcn_perm(pb_hi, pb_lo, k3));
+            if (__builtin_expect(miss != 0, 0)) {
+                cw[0] = swar_cols(c.x, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                cw[1] = swar_cols(c.y, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                cw[2] = swar_cols(c.z, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+                cw[3] = swar_cols(c.w, sh, pb_lo, pb_hi, pc_lo, pc_hi);
+            } else {
+                cw[0] = __builtin_amdgcn_perm(pc_hi, pc_lo, k0);
+                cw[1] = __builtin_amdgcn_perm(pc_hi, pc_lo, k1);
+                cw[2] = __builtin_amdgcn_perm(pc_hi, pc_lo, k2);
+                cw[3] = __builtin_amdgcn_perm(pc_hi, pc_lo, k3);
+            }
         } else {
             cw[0] = c.x;
             cw[1] = c.y;
@@ -526,13 +607,13 @@ struct WmWalk {
 
     // Copy what this walker reads from LDS (no barrier).
     template <int W>
-    __device__ __forceinline__ static void load(const WmDev &a, uint8_t *smem)
+    __device__ __forceinline__ static void load(const WmDev &a)
     {
         if (InLds)
-            copy_to_lds<W>(smem, a.tables, a.table_bytes);
+            copy_to_lds<W>(LDS_TAB_OFF, a.tables, a.table_bytes);
     }
 
-    __device__ __forceinline__ void bind(const WmDev &a, uint8_t *smem)
+    __device__ __forceinline__ void bind(const WmDev &a)
     {
         m = a.m;
         B = a.B;
@@ -540,7 +621,11 @@ struct WmWalk {
         kl = a.key_len;
         hmask = (1u << (2 * B)) - 1u;
         kmask = kl >= 16 ? 0xffffffffu : ((1u << (2 * kl)) - 1u);
-        const uint8_t *base = InLds ? smem : a.tables;
+        typename TabPtr<InLds, uint8_t>::type base;
+        if constexpr (InLds)
+            base = lds_at<const uint8_t>(LDS_TAB_OFF);
+        else
+            base = (glb_cptr<uint8_t>)a.tables;
         sh16 = (typename TabPtr<InLds, uint16_t>::type)base;
         boff = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_boff);
         bkey = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bkey);
@@ -549,10 +634,10 @@ struct WmWalk {
     }
 
     template <int W>
-    __device__ __forceinline__ void setup(const WmDev &a, uint8_t *smem, uint32_t /*unused*/)
+    __device__ __forceinline__ void setup(const WmDev &a, uint32_t /*unused*/)
     {
-        load<W>(a, smem);
-        bind(a, smem);
+        load<W>(a);
+        bind(a);
         __syncthreads();
     }
 
@@ -787,10 +872,14 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
                                                  uint32_t dupfree, uint32_t unused)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ TextDesc s_td;
-    __shared__ uint64_t s_tile;
-    __shared__ uint32_t s_epoch;
-    __shared__ uint64_t s_scan[Walk::ILP * (W / 64) + 1];
+    static_assert(Walk::ILP * (W / 64) + 1 <= LDS_SCAN_WORDS, "scan words");
+    if (!lds_layout_ok(smem, sd.hdr))
+        return;
+    LdsHdr *const H = (LdsHdr *)lds_at<LdsHdr>(LDS_HDR_OFF);
+    TextDesc &s_td = H->td;
+    uint64_t &s_tile = H->tile;
+    uint32_t &s_epoch = H->epoch;
+    uint64_t *const s_scan = H->scan;
 
     // Launch constants as plain values (no by-reference use of the argument
     // structs, which would place them in private memory).
@@ -805,7 +894,7 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     const uint32_t m = a.m;
 
     Walk wk;
-    wk.template setup<W>(a, smem, unused);
+    wk.template setup<W>(a, unused);
     if (threadIdx.x == 0)
         s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
@@ -848,14 +937,14 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
 // differs from the one it holds.
 // ---------------------------------------------------------------------------
 template <class Walk, int W, class Dev>
-__device__ __forceinline__ void batch_chunk(const Dev &dev, uint8_t *smem, glb_cptr<uint8_t> text,
+__device__ __forceinline__ void batch_chunk(const Dev &dev, glb_cptr<uint8_t> text,
                                             uint64_t n, mpm_match *out, uint64_t cap,
                                             uint64_t *total, uint64_t first_g, uint64_t nt,
                                             uint64_t g, uint32_t L, uint32_t epoch, uint32_t *hdr,
                                             uint64_t *status, uint64_t *s_scan)
 {
     Walk wk;
-    wk.bind(dev, smem);
+    wk.bind(dev);
     process_chunk<Walk, W>(wk, text, n, out, cap, total, first_g, nt, g, L, dev.m, epoch,
                            (glb_cptr<uint32_t>)dev.uoff, (glb_cptr<uint32_t>)dev.uids, dev.dupfree,
                            hdr, status, s_scan);
@@ -865,10 +954,14 @@ template <int W>
 __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ BatchText s_bt;
-    __shared__ uint64_t s_tile;
-    __shared__ uint32_t s_epoch;
-    __shared__ uint64_t s_scan[W / 64 + 1];
+    static_assert(W / 64 + 1 <= LDS_SCAN_WORDS, "scan words");
+    if (!lds_layout_ok(smem, bd.hdr))
+        return;
+    LdsHdr *const H = (LdsHdr *)lds_at<LdsHdr>(LDS_HDR_OFF);
+    BatchText &s_bt = H->bt;
+    uint64_t &s_tile = H->tile;
+    uint32_t &s_epoch = H->epoch;
+    uint64_t *const s_scan = H->scan;
 
     const uint32_t ntexts = bd.ntexts;
     const uint64_t ntiles = bd.ntiles;
@@ -905,10 +998,10 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
         const uint32_t key = (ix << 8) | kind;
         if (key != loaded) {
             switch (kind & BK_WALK_MASK) {
-            case BK_AC16_LDS: AcWalk<uint16_t, true, false, 1>::load<W>(bi.ac, smem); break;
-            case BK_AC16_GLB: AcWalk<uint16_t, false, false, 1>::load<W>(bi.ac, smem); break;
-            case BK_AC32_GLB: AcWalk<uint32_t, false, false, 1>::load<W>(bi.ac, smem); break;
-            case BK_WM_LDS: WmWalk<true>::load<W>(bi.wm, smem); break;
+            case BK_AC16_LDS: AcWalk<uint16_t, true, false, 1>::load<W>(bi.ac); break;
+            case BK_AC16_GLB: AcWalk<uint16_t, false, false, 1>::load<W>(bi.ac); break;
+            case BK_AC32_GLB: AcWalk<uint32_t, false, false, 1>::load<W>(bi.ac); break;
+            case BK_WM_LDS: WmWalk<true>::load<W>(bi.wm); break;
             default: break;
             }
             __syncthreads();
@@ -927,40 +1020,40 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
         switch (kind & BK_WALK_MASK) {
         case BK_AC16_LDS:
             if (swar)
-                batch_chunk<AcWalk<uint16_t, true, true, 1>, W>(bi.ac, smem, text, n, out, cap, total,
+                batch_chunk<AcWalk<uint16_t, true, true, 1>, W>(bi.ac, text, n, out, cap, total,
                                                                 first_g, nt, g, L, epoch, hdr,
                                                                 status, s_scan);
             else
-                batch_chunk<AcWalk<uint16_t, true, false, 1>, W>(bi.ac, smem, text, n, out, cap,
+                batch_chunk<AcWalk<uint16_t, true, false, 1>, W>(bi.ac, text, n, out, cap,
                                                                  total, first_g, nt, g, L, epoch,
                                                                  hdr, status, s_scan);
             break;
         case BK_AC16_GLB:
             if (swar)
-                batch_chunk<AcWalk<uint16_t, false, true, 1>, W>(bi.ac, smem, text, n, out, cap,
+                batch_chunk<AcWalk<uint16_t, false, true, 1>, W>(bi.ac, text, n, out, cap,
                                                                  total, first_g, nt, g, L, epoch,
                                                                  hdr, status, s_scan);
             else
-                batch_chunk<AcWalk<uint16_t, false, false, 1>, W>(bi.ac, smem, text, n, out, cap,
+                batch_chunk<AcWalk<uint16_t, false, false, 1>, W>(bi.ac, text, n, out, cap,
                                                                   total, first_g, nt, g, L, epoch,
                                                                   hdr, status, s_scan);
             break;
         case BK_AC32_GLB:
             if (swar)
-                batch_chunk<AcWalk<uint32_t, false, true, 1>, W>(bi.ac, smem, text, n, out, cap,
+                batch_chunk<AcWalk<uint32_t, false, true, 1>, W>(bi.ac, text, n, out, cap,
                                                                  total, first_g, nt, g, L, epoch,
                                                                  hdr, status, s_scan);
             else
-                batch_chunk<AcWalk<uint32_t, false, false, 1>, W>(bi.ac, smem, text, n, out, cap,
+                batch_chunk<AcWalk<uint32_t, false, false, 1>, W>(bi.ac, text, n, out, cap,
                                                                   total, first_g, nt, g, L, epoch,
                                                                   hdr, status, s_scan);
             break;
         case BK_WM_LDS:
-            batch_chunk<WmWalk<true>, W>(bi.wm, smem, text, n, out, cap, total, first_g, nt, g, L,
+            batch_chunk<WmWalk<true>, W>(bi.wm, text, n, out, cap, total, first_g, nt, g, L,
                                          epoch, hdr, status, s_scan);
             break;
         default:
-            batch_chunk<WmWalk<false>, W>(bi.wm, smem, text, n, out, cap, total, first_g, nt, g, L,
+            batch_chunk<WmWalk<false>, W>(bi.wm, text, n, out, cap, total, first_g, nt, g, L,
                                           epoch, hdr, status, s_scan);
             break;
         }

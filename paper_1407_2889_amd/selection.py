@@ -82,10 +82,36 @@ def uniform_choice(k: int, valid_row: np.ndarray) -> int:
     return tune.VARIANTS.index((a, L, W, tune.PLACEMENTS[1]))
 
 
+def run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps: int = 5):
+    """Capture the batch with request i under variant choice[i] and return
+    (median replay ms, totals, launch count). ms_known [R, 24] (or None)
+    gives the per-request times the queue order is built from."""
+    import torch
+    R = len(pset)
+    idx = [pset[i].index(int(choice[i])) for i in range(R)]
+    var = [tune.variant_struct(int(choice[i])) for i in range(R)]
+    hint = None
+    if ms_known is not None:
+        hint = [tune.chunk_cost_hint(int(choice[i]), float(ms_known[i, int(choice[i])]),
+                                     int(lens[i]), pset[i].m) for i in range(R)]
+    bs = _batch.BatchScan(arena, offs, lens, idx, var, caps, cost_hints=hint)
+    bs.capture()
+    bs.replay()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, z in ev:
+        a.record()
+        bs.replay()
+        z.record()
+    torch.cuda.synchronize()
+    tms = float(np.median([a.elapsed_time(z) for a, z in ev]))
+    return tms, bs.totals_host(), bs.groups
+
+
 def evaluate(b: synth.Batch, tuner: tune.Tuner, selector: Selector, default_variant: int,
              margin: float = 0.05, reps: int = 5, log=None):
     """Run the three policies on batch b; returns a result dict."""
-    import torch
     sets_idx = [tune.PatternSetIndexes.build(ps.patterns) for ps in b.sets]
     arena, offs, lens = _batch.pack_texts(b.texts)
     R = len(b.texts)
@@ -122,26 +148,7 @@ def evaluate(b: synth.Batch, tuner: tune.Tuner, selector: Selector, default_vari
     ms_learned = np.where(fallback[:, None], ms, ms_pred)
 
     def run(choice, ms_known):
-        idx = [pset[i].index(int(choice[i])) for i in range(R)]
-        var = [tune.variant_struct(int(choice[i])) for i in range(R)]
-        hint = None
-        if ms_known is not None:
-            hint = [tune.chunk_cost_hint(int(choice[i]), float(ms_known[i, int(choice[i])]),
-                                         int(lens[i]), pset[i].m) for i in range(R)]
-        bs = _batch.BatchScan(arena, offs, lens, idx, var, caps, cost_hints=hint)
-        bs.capture()
-        bs.replay()
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(reps)]
-        for a, z in ev:
-            a.record()
-            bs.replay()
-            z.record()
-        torch.cuda.synchronize()
-        tms = float(np.median([a.elapsed_time(z) for a, z in ev]))
-        tot = bs.totals_host()
-        return tms, tot, bs.groups
+        return run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps)
 
     total_bytes = int(np.sum(lens))
     res = {"requests": R, "text_bytes": total_bytes}
@@ -174,4 +181,7 @@ def evaluate(b: synth.Batch, tuner: tune.Tuner, selector: Selector, default_vari
         "default": float(ms[np.arange(R), default].sum() / tbest - 1)}
     res["default_variant"] = list(tune.VARIANTS[default_variant])
     res["matches"] = int(np.sum(caps))
+    res["_state"] = dict(arena=arena, offs=offs, lens=lens, pset=pset, caps=caps, ms=ms,
+                         ms_pred=ms_pred, exh=exh, final=final, default=default,
+                         learned=learned, fallback=fallback)
     return res
