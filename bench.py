@@ -11,7 +11,15 @@ scanned (n by AC, n by WM) per second. The line also carries the roofline of
 the dominant kernel (HIP events on the launch stream) and the CPU oracle's
 throughput on the same text (single thread).
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu] [--workload est256|small]
+Other workloads (one JSON line each):
+  --workload sweep   1 GiB EST-shaped text against nine pattern sets
+                     (d in {1k, 10k, 100k} x m in {8, 16, 32}), AC and WM;
+  --workload batch   4,096 texts with 64 pattern sets run as one replayed
+                     graph per selection policy (exhaustive autotune, learned
+                     selector with fallback, fixed default), after a timing
+                     database of --train-requests requests trains the selector.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--workload est256|small|sweep|batch]
 """
 
 from __future__ import annotations
@@ -104,6 +112,135 @@ def cpu_baseline(text, P, sample_bytes: int):
     }
 
 
+def time_scans(sc, dev_text, steps: int, warmup: int, stream) -> float:
+    """Mean kernel milliseconds of `steps` scans (HIP events on the stream)."""
+    import torch
+    for _ in range(warmup):
+        sc.scan_async(dev_text)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        sc.scan_async(dev_text)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def run_sweep(args):
+    """Pattern-set sweep: 1 GiB EST-shaped text, d in {1k, 10k, 100k} x m in
+    {8, 16, 32}, 10% planted; every (set, algorithm) scanned with the full
+    sorted list written. One JSON line with one record per (set, algorithm):
+    text GB/s, the HBM roofline fraction of the algorithmic bytes, the match
+    count and a digest of the per-pattern counts."""
+    import torch
+    import paper_1407_2889_amd as mpm
+    import synth
+    log("[bench] generating 1 GiB EST-shaped text")
+    text = synth.workload_sweep_text()
+    n = len(text)
+    dev = torch.from_numpy(text).cuda()
+    stream = torch.cuda.current_stream()
+    rows = []
+    t_all = 0.0
+    for d in synth.SWEEP_D:
+        for m in synth.SWEEP_M:
+            ps = synth.workload_sweep_set(text, d, m)
+            lists = {}
+            for algo in ("ac", "wm"):
+                t0 = time.perf_counter()
+                ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(ps.patterns, upload=True)
+                build_s = time.perf_counter() - t0
+                info = ix.info()
+                v = mpm.variant(**DEFAULT_VARIANTS[algo])
+                count = mpm.Scanner(ix, n, 0, v)
+                count.scan_async(dev)
+                torch.cuda.synchronize()
+                M = int(count.total.item())
+                sc = mpm.Scanner(ix, n, M, v)
+                kms = time_scans(sc, dev, args.steps, args.warmup, stream)
+                t_all += kms * args.steps
+                lists[algo] = sc.out[:M]
+                counts = torch.bincount(sc.out[:M, 1].to(torch.int64), minlength=d)
+                alg_bytes = n + 8 * M + info["table_bytes"]
+                rows.append({
+                    "d": d, "m": m, "algo": algo, "gbps": round(n / (kms * 1e-3) / 1e9, 2),
+                    "kernel_ms": round(kms, 4), "matches": M,
+                    "roofline_frac": round(alg_bytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "table_bytes": info["table_bytes"],
+                    "states": info["n_states"] if algo == "ac" else None,
+                    "wm_block": info["wm_block"] if algo == "wm" else None,
+                    "placement": "lds" if info["table_bytes"] + 1024 <= 160 * 1024 else "global",
+                    "patterns_hit": int((counts > 0).sum()), "max_count": int(counts.max()),
+                    "build_s": round(build_s, 3)})
+                log(f"[bench] d={d} m={m} {algo}: {rows[-1]['gbps']} GB/s, {M} matches")
+                del sc, count, ix
+            if not torch.equal(lists["ac"], lists["wm"]):
+                raise SystemExit(f"AC and WM disagree at d={d} m={m}")
+            del lists
+            torch.cuda.empty_cache()
+    line = {"metric": METRIC, "workload": "sweep",
+            "config": {"workload": "1 GiB EST-shaped DNA text (seed 4); d in {1000, 10000, 100000} x "
+                                   "m in {8, 16, 32}, 10% planted (seeds 10-18)", "n_bytes": n,
+                       "variants": DEFAULT_VARIANTS},
+            "steps": args.steps, "warmup": args.warmup, "dtype": "u8", "data": "synthetic",
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
+def run_batched(args):
+    """Batched workload with variant selection: a timing database of seeded
+    training requests, the selector trained on it, then the 4,096-text batch
+    run as one replayed graph per policy (exhaustive, learned with fallback,
+    fixed default). One JSON line."""
+    import torch
+    import synth
+    from paper_1407_2889_amd import learn, selection, tune
+    t_start = time.perf_counter()
+    log(f"[bench] timing database: {args.train_requests} requests")
+    stream, sets, reqs = selection.training_requests(args.train_requests, 48, seed=1000,
+                                                     stream_bytes=256 << 20)
+    sd = torch.from_numpy(stream).cuda()
+    sidx = [tune.PatternSetIndexes.build(p.patterns) for p in sets]
+    tuner = tune.Tuner()
+    t0 = time.perf_counter()
+    feats, ms = selection.build_db(tuner, sidx, sd, reqs, log=log)
+    t_db = time.perf_counter() - t0
+    del sd, sidx
+    t0 = time.perf_counter()
+    sel = learn.Selector.fit(feats, ms)
+    t_fit = time.perf_counter() - t0
+    kdef = selection.best_uniform_variant(ms)
+    log(f"[bench] db {t_db:.1f}s, fit {t_fit:.1f}s, default variant {tune.VARIANTS[kdef]}")
+    log(f"[bench] batch: {args.batch_texts} texts")
+    b = synth.workload_batch(n_texts=args.batch_texts, n_sets=64, seed=20)
+    res = selection.evaluate(b, tuner, sel, kdef, log=log)
+    res.pop("_state")
+    line = {"metric": METRIC, "workload": "batch",
+            "value": round(res["learned_gbps"], 2), "unit": "GB/s",
+            "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": f"{args.batch_texts} EST-shaped texts, log-uniform 1 KiB-4 MiB "
+                                   "(seed 20), 64 pattern sets d log-uniform 100-50k, m in "
+                                   "{8,12,16,24,32}, 10% planted (seed 21), pairing seed 22",
+                       "train_requests": args.train_requests},
+            "exhaustive_gbps": round(res["exhaustive_gbps"], 2),
+            "learned_gbps": round(res["learned_gbps"], 2),
+            "default_gbps": round(res["default_gbps"], 2),
+            "regret": round(res["regret"], 4), "fallback_rate": round(res["fallback_rate"], 4),
+            "gain_over_default": round(res["gain_over_default"], 4),
+            "totals_agree": res["totals_agree"], "matches": res["matches"],
+            "text_bytes": res["text_bytes"], "launches": {k: res[f"{k}_launches"] for k in
+                                                          ("exhaustive", "learned", "default")},
+            "pick_agreement": round(res["pick_agreement"], 4),
+            "time_regret_isolated": {k: round(v, 4) for k, v in res["time_regret_isolated"].items()},
+            "selection_overhead_s": {k: round(v, 4) for k, v in res["selection_overhead_s"].items()},
+            "timing_db_s": round(t_db, 1), "fit_s": round(t_fit, 1),
+            "default_variant": res["default_variant"],
+            "wall_s": round(time.perf_counter() - t_start, 1)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,13 +249,20 @@ def main():
     ap.add_argument("--workload", default="est256")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample-mib", type=int, default=256)
-    ap.add_argument("--ac", default=None, help="AC variant as L,W,placement")
-    ap.add_argument("--wm", default=None, help="WM variant as L,W,placement")
+    ap.add_argument("--ac", default=None, help="AC variant as L,W,placement[,flags]")
+    ap.add_argument("--wm", default=None, help="WM variant as L,W,placement[,flags]")
+    ap.add_argument("--train-requests", type=int, default=5000, help="batch: timing database size")
+    ap.add_argument("--batch-texts", type=int, default=4096, help="batch: texts in the batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the scan shards by contiguous text ranges, see the design notes", file=sys.stderr)
+              "the scan shards by contiguous text ranges across GPUs, but this build "
+              "measures one GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "sweep":
+        return run_sweep(args)
+    if args.workload == "batch":
+        return run_batched(args)
 
     import torch
     import paper_1407_2889_amd as mpm
@@ -127,8 +271,9 @@ def main():
     for k in ("ac", "wm"):
         s = getattr(args, k)
         if s:
-            L, W, Pl = (int(x) for x in s.split(","))
-            variants[k] = dict(lane_bytes=L, block_threads=W, placement=Pl)
+            f = [int(x) for x in s.split(",")]
+            variants[k] = dict(lane_bytes=f[0], block_threads=f[1], placement=f[2],
+                               **({"flags": f[3]} if len(f) > 3 else {}))
 
     log(f"[bench] generating workload {args.workload}")
     text, ps, desc = workload(args.workload)

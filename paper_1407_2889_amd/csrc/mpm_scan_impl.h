@@ -99,6 +99,17 @@ __device__ __forceinline__ uint32_t in_vgpr(uint32_t x)
 }
 static const uint32_t SPIN_LIMIT = 1u << 24;
 
+// The same value, hidden from the optimizer. A walk repeated to report its
+// occurrences starts from an opaque copy of its first state: otherwise the
+// compiler proves that it retraces the first walk and keeps that walk's states
+// (one per byte) for it instead, which costs far more registers than the
+// rare second walk costs time.
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // ---------------------------------------------------------------------------
 // Look-back status words
 // ---------------------------------------------------------------------------
@@ -503,50 +514,269 @@ struct AcWalk {
         walk_from(s, text, p, end, cb);
     }
 
-    // Two walks in lockstep (bytes [pa, ea) and [pb, eb), both starting on
-    // 16-byte boundaries): two independent lookup chains per lane. The common
-    // length runs interleaved with 16-byte loads two pieces ahead; the rest of
-    // each walk runs alone.
-    template <class FA, class FB>
-    __device__ __forceinline__ void walk2(glb_cptr<uint8_t> text, uint64_t pa, uint64_t ea,
-                                          uint64_t pb, uint64_t eb, FA &cba, FB &cbb) const
+    // Steps of one 16-byte piece whose column words are cw, from state s:
+    // returns the largest state reached (a terminal state shows as a value
+    // >= first_term), s is left at the state after the piece.
+    __device__ __forceinline__ uint32_t steps16(uint32_t &s, const uint32_t (&cw)[4]) const
     {
-        uint32_t sa = 0, sb = 0;
-        const uint64_t la = ea > pa ? ea - pa : 0, lb = eb > pb ? eb - pb : 0;
-        const uint64_t common = (la < lb ? la : lb) & ~15ull;
-        if (common) {
-            glb_cptr<v4u> qa = (glb_cptr<v4u>)(text + pa);
-            glb_cptr<v4u> qb = (glb_cptr<v4u>)(text + pb);
-            const uint64_t np = common / 16;
-            v4u a0 = qa[0], b0 = qb[0];
-            v4u a1 = qa[np > 1 ? 1 : 0], b1 = qb[np > 1 ? 1 : 0];
-            for (uint64_t k = 0; k < np; ++k) {
-                const uint64_t k2 = k + 2 < np ? k + 2 : k;
-                const v4u a2 = qa[k2], b2 = qb[k2];
-                uint32_t cwa[4], cwb[4];
-                cols16(a0, cwa);
-                cols16(b0, cwb);
-                uint32_t sta[16], stb[16];
-                uint32_t mxa = 0, mxb = 0;
+        uint32_t mx = 0;
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    sa = next(sa, col_of(cwa, j));
-                    sb = next(sb, col_of(cwb, j));
-                    sta[j] = sa;
-                    stb[j] = sb;
-                    mxa = max(mxa, sa);
-                    mxb = max(mxb, sb);
-                }
-                report16(sta, mxa, pa + 16 * k, cba);
-                report16(stb, mxb, pb + 16 * k, cbb);
-                a0 = a1;
-                a1 = a2;
-                b0 = b1;
-                b1 = b2;
+        for (int k = 0; k < 16; ++k) {
+            s = next(s, col_of(cw, k));
+            mx = max(mx, s);
+        }
+        return mx;
+    }
+
+    // The first cnt bytes of a piece again from state s, reporting every
+    // terminal state (q = text position of the piece's first byte). Runs only
+    // for pieces that reached a terminal state.
+    template <class F>
+    __device__ __forceinline__ void report_piece(uint32_t s, const uint32_t (&cw)[4], uint32_t cnt,
+                                                 uint64_t q, F &cb) const
+    {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if ((uint32_t)k < cnt) {
+                s = next(s, col_of(cw, k));
+                if (s >= first_term)
+                    cb(q + k + 1 - m, s - first_term);
             }
         }
-        walk_from(sa, text, pa + common, ea, cba);
-        walk_from(sb, text, pb + common, eb, cbb);
+    }
+
+    // Column byte offset of byte k of a piece packed as two words of
+    // nibbles: word k >> 3, bytes 0-3 of the word's half in the low nibbles,
+    // bytes 4-7 in the high nibbles.
+    __device__ __forceinline__ static uint32_t col_nib(uint32_t p0, uint32_t p1, int k)
+    {
+        const uint32_t w = k < 8 ? p0 : p1;
+        const int kk = k & 7;
+        return (w >> (8 * (kk & 3) + 4 * (kk >> 2))) & 15u;
+    }
+
+    // Steps of a packed piece from state s (as steps16).
+    __device__ __forceinline__ uint32_t steps_nib(uint32_t &s, uint32_t p0, uint32_t p1) const
+    {
+        uint32_t mx = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            s = next(s, col_nib(p0, p1, k));
+            mx = max(mx, s);
+        }
+        return mx;
+    }
+
+    // The first cnt bytes of a packed piece from state s (left at the state
+    // after them), reporting every terminal state (q = text position of the
+    // piece's first byte).
+    template <class F>
+    __device__ __forceinline__ void report_nib(uint32_t &s, uint32_t p0, uint32_t p1, uint32_t cnt,
+                                               uint64_t q, F &cb) const
+    {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if ((uint32_t)k < cnt) {
+                s = next(s, col_nib(p0, p1, k));
+                if (s >= first_term)
+                    cb(q + k + 1 - m, s - first_term);
+            }
+        }
+    }
+
+    // I walks in lockstep over whole 128-byte lines (I independent lookup
+    // chains per lane). Walk c covers bytes [p[c], e[c]); every p[c] is
+    // 128-byte aligned in memory. Each walk keeps two lines: the one being
+    // walked, its 128 column offsets packed as nibbles (16 registers), and
+    // the next one in flight as raw bytes (32 registers), requested as a
+    // whole line with eight back-to-back 16-byte loads: lines whose pieces
+    // are requested far apart are evicted from L2 between requests and
+    // fetched from HBM again. With one walk, the first bytes past the common
+    // lines (the m - 1 overlap into the next lane's range, which that lane
+    // reads at its start) are loaded with the first line, from the same
+    // cache line fill, instead of by a second fetch at the end.
+    // cb(c, start, u) reports an occurrence found by walk c.
+    template <int I, class F>
+    __device__ __forceinline__ void walk_lines(glb_cptr<uint8_t> text, uint64_t n,
+                                               const uint64_t (&p)[I], const uint64_t (&e)[I],
+                                               F &cb) const
+    {
+        static_assert(Swar && sizeof(St) == 2, "walk_lines packs 4-bit column offsets");
+        constexpr int NT = I == 1 ? 2 : 0;  // tail pieces loaded up front
+        uint64_t common = e[0] - p[0];
+#pragma unroll
+        for (int c = 1; c < I; ++c)
+            common = min(common, e[c] - p[c]);
+        const uint32_t nl = (uint32_t)(common >> 7);
+        uint32_t s[I];
+        v4u raw[I][8];
+        uint32_t cur[I][16];
+        v4u tail[I][NT > 0 ? NT : 1];
+        auto pack = [&](int c) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint32_t cw[4];
+                cols16(raw[c][j], cw);
+                cur[c][2 * j] = cw[0] | (cw[1] << 4);
+                cur[c][2 * j + 1] = cw[2] | (cw[3] << 4);
+            }
+        };
+        auto fetch = [&](int c, uint32_t l) {
+            glb_cptr<v4u> q = (glb_cptr<v4u>)(text + p[c] + ((uint64_t)l << 7));
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                raw[c][j] = q[j];
+        };
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+            s[c] = 0;
+            fetch(c, 0);
+            const uint64_t t0 = p[c] + ((uint64_t)nl << 7);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const uint64_t tq = t0 + 16 * j;
+                tail[c][j] = (tq < e[c] && tq + 16 <= n) ? *(glb_cptr<v4u>)(text + tq) : v4u{0, 0, 0, 0};
+            }
+        }
+        // One walk double-buffers: the next line is in flight while the
+        // current one is walked. Several walks fetch their next lines only
+        // once the current ones are done and wait for them (the other waves
+        // of the CU cover the wait): the registers of a second line per walk
+        // would not fit.
+        constexpr bool DB = I == 1;
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+            pack(c);
+            if (DB)
+                fetch(c, nl > 1 ? 1 : 0);
+        }
+        for (uint32_t l = 0; l < nl; ++l) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint32_t s0[I], mx[I];
+#pragma unroll
+                for (int c = 0; c < I; ++c) {
+                    s0[c] = s[c];
+                    mx[c] = 0;
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+#pragma unroll
+                    for (int c = 0; c < I; ++c) {
+                        s[c] = next(s[c], col_nib(cur[c][2 * j], cur[c][2 * j + 1], k));
+                        mx[c] = max(mx[c], s[c]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < I; ++c) {
+                    if (mx[c] >= first_term) {
+                        auto one = [&](uint64_t st, uint32_t u) { cb(c, st, u); };
+                        uint32_t st = opaque(s0[c]);
+                        report_nib(st, cur[c][2 * j], cur[c][2 * j + 1], 16,
+                                   p[c] + ((uint64_t)l << 7) + 16 * j, one);
+                    }
+                }
+            }
+            if (l + 1 < nl) {
+                if (DB) {
+                    // the next line into the packed buffer, the one after it
+                    // (the last line again at the end) into flight
+                    const uint32_t l2 = l + 2 < nl ? l + 2 : nl - 1;
+#pragma unroll
+                    for (int c = 0; c < I; ++c) {
+                        pack(c);
+                        fetch(c, l2);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < I; ++c)
+                        fetch(c, l + 1);
+#pragma unroll
+                    for (int c = 0; c < I; ++c)
+                        pack(c);
+                }
+            }
+        }
+        // the tail: preloaded pieces, then whatever lies beyond them
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+            auto one = [&](uint64_t st, uint32_t u) { cb(c, st, u); };
+            uint64_t q = p[c] + ((uint64_t)nl << 7);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                if (q < e[c] && q + 16 <= n) {
+                    uint32_t cw[4];
+                    cols16(tail[c][j], cw);
+                    const uint32_t cnt = (uint32_t)min((uint64_t)16, e[c] - q);
+                    const uint32_t s0 = s[c];
+                    if (cnt == 16) {
+                        if (steps16(s[c], cw) >= first_term)
+                            report_piece(opaque(s0), cw, 16, q, one);
+                    } else {
+                        report_piece(s0, cw, cnt, q, one);
+                    }
+                    q += cnt;
+                }
+            }
+            if (q < e[c])
+                walk_rest(s[c], text, q, e[c], one);
+        }
+    }
+
+    // Bytes [p, end) from state s, without the line ring: 16-byte pieces
+    // where they are aligned, single bytes elsewhere. Used for the rare
+    // remainders of walk_lines and for second walks of a range.
+    template <class F>
+    __device__ __forceinline__ void walk_rest(uint32_t &s, glb_cptr<uint8_t> text, uint64_t p,
+                                              uint64_t end, F &cb) const
+    {
+        while (p < end) {
+            if ((((uintptr_t)(text + p)) & 15u) == 0 && p + 16 <= end) {
+                uint32_t cw[4];
+                cols16(*(glb_cptr<v4u>)(text + p), cw);
+                const uint32_t s0 = s;
+                if (steps16(s, cw) >= first_term)
+                    report_piece(opaque(s0), cw, 16, p, cb);
+                p += 16;
+            } else {
+                s = next(s, Swar ? byte_col((uint32_t)text[p]) : (uint32_t)cls[text[p]]);
+                if (s >= first_term)
+                    cb(p + 1 - m, s - first_term);
+                ++p;
+            }
+        }
+    }
+
+    // Column byte offset of one byte (Swar: the code's column when the byte
+    // is the code's expected byte, else column 0).
+    __device__ __forceinline__ uint32_t byte_col(uint32_t b) const
+    {
+        const uint32_t code = (b >> sh) & 7u;
+        const uint32_t ex = __builtin_amdgcn_perm(pb_hi, pb_lo, code) & 0xffu;
+        const uint32_t col = __builtin_amdgcn_perm(pc_hi, pc_lo, code) & 0xffu;
+        return ex == b ? col : 0u;
+    }
+
+    // The range of a lane again (the write pass of a lane with more
+    // occurrences than it kept): the plain walk, which keeps this rarely run
+    // copy small.
+    template <class F>
+    __device__ __forceinline__ void lane_again(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                               uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        if (lo >= hi)
+            return;
+        uint64_t end = base + hi + m - 1;
+        if (end > n)
+            end = n;
+        uint32_t s = 0;
+        walk_rest(s, text, base + lo, end, cb);
+    }
+
+    // Whether walk c's start is where walk_lines can take it.
+    __device__ __forceinline__ static bool line_aligned(glb_cptr<uint8_t> text, uint64_t p)
+    {
+        return (((uintptr_t)(text + p)) & 127u) == 0;
     }
 
     // Lane range: starts [lo, hi) relative to the chunk at text offset base.
@@ -559,6 +789,14 @@ struct AcWalk {
         uint64_t end = base + hi + m - 1;
         if (end > n)
             end = n;
+        if constexpr (Swar && Ilp == 1 && sizeof(St) == 2) {
+            if (line_aligned(text, base + lo) && end - (base + lo) >= 128) {
+                const uint64_t pp[1] = {base + lo}, ee[1] = {end};
+                auto one = [&](int, uint64_t st, uint32_t u) { cb(st, u); };
+                walk_lines<1>(text, n, pp, ee, one);
+                return;
+            }
+        }
         walk(text, base + lo, end, cb);
     }
 
@@ -569,9 +807,8 @@ struct AcWalk {
                                           uint32_t lo0, uint32_t hi0, uint32_t lo1, uint32_t hi1,
                                           FA &&cba, FB &&cbb) const
     {
-        if (lo1 >= hi1 || (((uintptr_t)text) & 15u)) {
-            lane(text, n, base, lo0, hi0, cba);
-            lane(text, n, base, lo1, hi1, cbb);
+        if (lo1 >= hi1) {
+            lane_again(text, n, base, lo0, hi0, cba);
             return;
         }
         uint64_t ea = base + hi0 + m - 1, eb = base + hi1 + m - 1;
@@ -579,7 +816,25 @@ struct AcWalk {
             ea = n;
         if (eb > n)
             eb = n;
-        walk2(text, base + lo0, ea, base + lo1, eb, cba, cbb);
+        if constexpr (Swar && sizeof(St) == 2) {
+            if (line_aligned(text, base + lo0) && line_aligned(text, base + lo1) &&
+                ea - (base + lo0) >= 128 && eb - (base + lo1) >= 128) {
+                const uint64_t pp[2] = {base + lo0, base + lo1}, ee[2] = {ea, eb};
+                auto two = [&](int c, uint64_t st, uint32_t u) {
+                    if (c == 0)
+                        cba(st, u);
+                    else
+                        cbb(st, u);
+                };
+                walk_lines<2>(text, n, pp, ee, two);
+                return;
+            }
+        }
+        // misaligned text, short ranges or no register columns: one walk
+        // after the other, compact code
+        uint32_t sa = 0, sb = 0;
+        walk_rest(sa, text, base + lo0, ea, cba);
+        walk_rest(sb, text, base + lo1, eb, cbb);
     }
 };
 
@@ -749,6 +1004,13 @@ struct WmWalk {
             });
         flush();
     }
+
+    template <class F>
+    __device__ __forceinline__ void lane_again(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                               uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        lane(text, n, base, lo, hi, cb);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -838,7 +1100,7 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
                 if ((uint32_t)k < nu[v])
                     write_ids(out, cap, o, so[v][k], su[v][k], uoff, uids, dupfree);
         } else {
-            wk.lane(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
+            wk.lane_again(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
                 write_ids(out, cap, o, (uint32_t)start, u, uoff, uids, dupfree);
             });
         }
