@@ -387,9 +387,11 @@ static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
             ix->boff[bucket_of[h] + 1] = bcount[h];
     for (uint32_t b = 0; b < nb; b++)
         ix->boff[b + 1] += ix->boff[b];
-    // Filter key: codes of the (up to 16) characters just before the last
-    // block, first character in the low bits.
-    const uint32_t kl = std::min<uint32_t>(16, m - B);
+    // Filter key: codes of the characters just before the last block, first
+    // character in the low bits. The scan reads block and key from a 32-
+    // character history in which a window ends at most 16 characters before
+    // its end, so B + key_len <= 17.
+    const uint32_t kl = std::min<uint32_t>(std::min<uint32_t>(16, m - B), 17 - B);
     ix->key_len = kl;
     ix->bu.assign(ix->du, 0);
     ix->bkey.assign(ix->du, 0);

@@ -758,19 +758,24 @@ struct AcWalk {
     }
 
     // The range of a lane again (the write pass of a lane with more
-    // occurrences than it kept): the plain walk, which keeps this rarely run
-    // copy small.
+    // occurrences than it kept). One chain per lane: the same line walk as
+    // the first pass (texts with many occurrences send most lanes through
+    // here). Two chains per lane: the plain walk, which keeps this copy small.
     template <class F>
     __device__ __forceinline__ void lane_again(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
                                                uint32_t lo, uint32_t hi, F &&cb) const
     {
-        if (lo >= hi)
-            return;
-        uint64_t end = base + hi + m - 1;
-        if (end > n)
-            end = n;
-        uint32_t s = 0;
-        walk_rest(s, text, base + lo, end, cb);
+        if constexpr (Ilp == 1) {
+            lane(text, n, base, lo, hi, cb);
+        } else {
+            if (lo >= hi)
+                return;
+            uint64_t end = base + hi + m - 1;
+            if (end > n)
+                end = n;
+            uint32_t s = 0;
+            walk_rest(s, text, base + lo, end, cb);
+        }
     }
 
     // Whether walk c's start is where walk_lines can take it.
@@ -896,23 +901,17 @@ struct WmWalk {
         __syncthreads();
     }
 
-    // 32 bits of the 96-bit history {h2:h1:h0} from bit o (o <= 64).
-    __device__ __forceinline__ static uint32_t bits(uint32_t h0, uint32_t h1, uint32_t h2, uint32_t o)
-    {
-        const uint32_t q = o >> 5;
-        const uint32_t lo = q == 0 ? h0 : (q == 1 ? h1 : h2);
-        const uint32_t hi = q == 0 ? h1 : h2;
-        return __builtin_amdgcn_alignbit(hi, lo, o & 31u);
-    }
-
     // Window loop (Algorithm 5) over one lane's range, the text streamed
-    // through registers. The history keeps the 2-bit codes of the last 48
-    // characters read (positions [e-48, e), position q at bit 2(q-e+48)).
-    // Every window end nx < e is examined: the hash of its last B
-    // characters picks SHIFT; a zero shift sends the window to its bucket,
-    // where the filter key (codes of the key_len characters before the block)
-    // must equal the candidate's before the window is compared byte by byte
-    // with the pattern.
+    // through registers as 2-bit character codes. The history holds the
+    // codes of the last 32 characters read (positions [e-32, e), position q
+    // at bit 2(q-e+32) of {h1:h0}). Every window end nx < e is examined: the
+    // hash of its last B characters picks SHIFT; a zero shift sends the
+    // window to its bucket, where the filter key (codes of the key_len
+    // characters before the block) must equal the candidate's before the
+    // window is compared byte by byte with the pattern. Window ends are never
+    // more than 16 characters behind e (every append adds at most 16 and all
+    // earlier windows are done), and the builder keeps B + key_len <= 17, so
+    // block and key both lie in the history: each is one 64-bit shift.
     template <class F>
     __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
                                          uint32_t lo, uint32_t hi, F &&cb) const
@@ -927,7 +926,7 @@ struct WmWalk {
         const uint32_t end = (uint32_t)end64;
         uint32_t nx = p + m - 1;
         uint32_t e = p;
-        uint32_t h0 = 0, h1 = 0, h2 = 0;
+        uint64_t h = 0;
         uint32_t qn = 0;
         uint32_t qp[WM_QUEUE];  // window ends
         uint32_t qu[WM_QUEUE];
@@ -954,14 +953,20 @@ struct WmWalk {
             }
             qn = 0;
         };
+        // block bit (minus one, for the byte offset of a u16 entry) and key
+        // bit of the window ending at nx: c2 + 2 (nx - e) and that + 1 - 2 kl
+        const uint32_t c2 = 65u - 2u * B;
+        const uint32_t hmask2 = hmask << 1;
+        const uint32_t kdrop = 2u * kl - 1u;
         auto windows = [&]() {
             while (nx < e) {
-                const uint32_t o = 2u * (nx + 49 - e - B);
-                const uint32_t h = bits(h0, h1, h2, o) & hmask;
-                const uint32_t sv = sh16[h];
+                const uint32_t o2 = c2 + 2u * (nx - e);
+                const uint32_t hb = (uint32_t)(h >> o2) & hmask2;
+                const uint32_t sv = *(typename TabPtr<InLds, uint16_t>::type)(
+                    (typename TabPtr<InLds, uint8_t>::type)sh16 + hb);
                 if (sv & 0x8000u) {
                     const uint32_t b = sv & 0x7fffu;
-                    const uint32_t key = kl ? (bits(h0, h1, h2, o - 2u * kl) & kmask) : 0u;
+                    const uint32_t key = kl ? ((uint32_t)(h >> (o2 - kdrop)) & kmask) : 0u;
                     const uint32_t je = boff[b + 1];
                     for (uint32_t j = boff[b]; j < je; ++j) {
                         if (bkey[j] == key) {
@@ -985,9 +990,7 @@ struct WmWalk {
         stream_text(
             text, p, end,
             [&](uint32_t b, uint64_t) {
-                h0 = (h0 >> 2) | (h1 << 30);
-                h1 = (h1 >> 2) | (h2 << 30);
-                h2 = (h2 >> 2) | (((b >> csh) & 3u) << 30);
+                h = (h >> 2) | ((uint64_t)((b >> csh) & 3u) << 62);
                 e += 1;
                 windows();
             },
@@ -996,9 +999,7 @@ struct WmWalk {
                        (codes4(c.w, csh) << 24);
             },
             [&](uint32_t codes, uint64_t) {
-                h0 = h1;
-                h1 = h2;
-                h2 = codes;
+                h = (h >> 32) | ((uint64_t)codes << 32);
                 e += 16;
                 windows();
             });

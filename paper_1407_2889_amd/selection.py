@@ -131,7 +131,12 @@ def evaluate(b: synth.Batch, tuner: tune.Tuner, selector: Selector, default_vari
     # exhaustive autotuning of every request (the reference, and the source of
     # the fallback choices)
     t0 = time.perf_counter()
-    ms = np.stack([tuner.time_all(pset[i], texts[i]) for i in range(R)])
+    rows = []
+    for i in range(R):
+        rows.append(tuner.time_all(pset[i], texts[i]))
+        if log and (i + 1) % max(1, R // 10) == 0:
+            log(f"[select] exhaustive tuning {i + 1}/{R} ({time.perf_counter() - t0:.1f}s)")
+    ms = np.stack(rows)
     t_exh = time.perf_counter() - t0
     exh = np.argmin(ms, axis=1)
     t_fallback = t_exh * float(fallback.mean())
