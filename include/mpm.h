@@ -309,8 +309,9 @@ mpm_status mpm_mlp_adam(float *d_theta, const float *d_grad, float *d_m, float *
 /* ---------------------------------------------------------------------- */
 
 /* Copy the dense Aho-Corasick table. Rows are states in breadth-first order
- * (root 0; the d_unique depth-m states last, in ascending order of their
- * pattern strings); columns are 1 + n_classes: column 0 (bytes in no pattern)
+ * (root 0; the d_unique depth-m states last, state n_states - d_unique + u
+ * being distinct string u of mpm_export_unique); columns are 1 + n_classes:
+ * column 0 (bytes in no pattern)
  * leads to the root, column c to the state after the c-th smallest pattern
  * byte. classes receives the n_classes bytes (may be NULL).
  * table: n_states * (1 + n_classes) uint32 entries (may be NULL).
@@ -322,7 +323,9 @@ mpm_status mpm_export_wm_shift(const mpm_index *idx, uint8_t *shift);
 
 /* Copy the unique-string index: uoff (d_unique + 1 entries) and ids (d
  * entries) so that ids[uoff[u] .. uoff[u+1]) are the ascending pattern ids of
- * the u-th smallest distinct pattern string. Errors: EINVAL. */
+ * distinct pattern string u. Distinct strings are numbered with those that
+ * occur once in the pattern array first, then the repeated ones, each group
+ * in ascending string order. Errors: EINVAL. */
 mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids);
 
 /* ---------------------------------------------------------------------- */

@@ -75,6 +75,32 @@ static mpm_status dedup(const uint8_t *P, uint32_t d, uint32_t m, mpm_index *ix)
     ix->max_dup = std::max(ix->max_dup, run);
     ix->uoff.push_back(d);
     ix->du = (uint32_t)(ix->uoff.size() - 1);
+    // Number the distinct strings with a single id first, the repeated ones
+    // after them (each group in ascending string order): a reported string
+    // u < n_single then stands for exactly one id, and the scan needs the id
+    // lists only for the rest.
+    std::vector<uint32_t> single, multi;
+    for (uint32_t u = 0; u < ix->du; u++)
+        (ix->uoff[u + 1] - ix->uoff[u] == 1 ? single : multi).push_back(u);
+    ix->n_single = (uint32_t)single.size();
+    if (!multi.empty() && !single.empty()) {
+        std::vector<uint32_t> perm(single);
+        perm.insert(perm.end(), multi.begin(), multi.end());
+        std::vector<uint32_t> uoff2(1, 0), uids2;
+        std::vector<uint8_t> upats2;
+        uids2.reserve(d);
+        upats2.reserve(ix->upats.size());
+        for (uint32_t u : perm) {
+            for (uint32_t j = ix->uoff[u]; j < ix->uoff[u + 1]; j++)
+                uids2.push_back(ix->uids[j]);
+            uoff2.push_back((uint32_t)uids2.size());
+            upats2.insert(upats2.end(), ix->upats.begin() + (uint64_t)u * m,
+                          ix->upats.begin() + (uint64_t)(u + 1) * m);
+        }
+        ix->uoff.swap(uoff2);
+        ix->uids.swap(uids2);
+        ix->upats.swap(upats2);
+    }
     return MPM_OK;
 }
 
@@ -120,6 +146,7 @@ static mpm_status build_ac_tables(mpm_index *ix)
     // creation order (Algorithm 1).
     std::vector<int32_t> child;
     std::vector<uint32_t> depth;
+    std::vector<uint32_t> term(du);  // the depth-m state of each distinct string
     child.reserve(std::min<uint64_t>(max_nodes, 1u << 22) * C);
     child.assign(C, -1);
     depth.push_back(0);
@@ -137,6 +164,7 @@ static mpm_status build_ac_tables(mpm_index *ix)
             }
             q = nx;
         }
+        term[u] = (uint32_t)q;
     }
     const uint64_t S = depth.size();
 
@@ -153,6 +181,10 @@ static mpm_status build_ac_tables(mpm_index *ix)
                 order.push_back((uint32_t)w);
         }
     }
+    // The deepest level comes last in breadth-first order; number it in the
+    // order of the distinct strings, so that state first_term + u is string u.
+    for (uint32_t u = 0; u < du; u++)
+        order[S - du + u] = term[u];
     std::vector<uint32_t> newid(S);
     for (uint64_t k = 0; k < S; k++)
         newid[order[k]] = (uint32_t)k;
@@ -639,11 +671,17 @@ mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm
                     (unsigned long long)work_bytes, (unsigned long long)(WS_HEADER_BYTES + 8 * nt));
     if (nt == 0)
         return launch_zero_totals(nullptr, 0, d_total, stream);
-    st = resolve_variant(idx, v, nt, &cfg);
+    st = resolve_variant(idx, v, nt, &cfg, true);
     if (st)
         return st;
     ScanDev sd;
     memset(&sd, 0, sizeof sd);
+    if (cfg.csr_lds) {
+        sd.csr_uoff_words = csr_uoff_words(idx);
+        sd.csr_uids_words = csr_uids_words(idx);
+        sd.csr_uoff_lds = cfg.csr_lds;
+        sd.csr_uids_lds = cfg.csr_lds + 4 * sd.csr_uoff_words;
+    }
     sd.single = TextDesc{d_text, n, d_out, capacity, d_total, 0, nt};
     sd.multi = nullptr;
     sd.ntexts = 1;

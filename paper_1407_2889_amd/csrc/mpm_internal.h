@@ -32,6 +32,7 @@ struct AcDev {
     uint32_t m;
     uint32_t dfa_bytes;     // bytes of the table (multiple of 16)
     uint32_t dupfree;       // every distinct string has exactly one id
+    uint32_t n_single;      // distinct strings below this have one id each
     // Byte classes without a lookup table, usable when the pattern bytes
     // have distinct 3-bit codes (b >> swar_shift) & 7: perm_byte selects, per
     // code, the only byte with that code that is a pattern byte (or a byte
@@ -62,6 +63,7 @@ struct WmDev {
     uint32_t key_len;
     uint32_t table_bytes;
     uint32_t dupfree;
+    uint32_t n_single;
 };
 
 // One text of a launch. Tiles of a launch are numbered globally; a text
@@ -92,6 +94,10 @@ struct ScanDev {
     uint64_t ntiles;
     uint32_t *hdr;
     uint64_t *status;
+    // The distinct-string -> id CSR copied to LDS at these byte offsets
+    // (0: read from global memory), with its word counts.
+    uint32_t csr_uoff_lds, csr_uids_lds;
+    uint32_t csr_uoff_words, csr_uids_words;
 };
 
 // Batched launches: one descriptor per text (in queue order) and one per
@@ -143,6 +149,7 @@ static const uint32_t ST_EPOCH_MASK = (1u << 26) - 1;
 struct mpm_index {
     uint32_t algo = 0;
     uint32_t m = 0, d = 0, du = 0, max_dup = 0;
+    uint32_t n_single = 0;              // distinct strings 0..n_single-1 have one id each
     std::vector<uint32_t> uoff, uids;   // distinct strings -> ids
     std::vector<uint8_t> upats;         // du * m, ascending strings
 
@@ -183,9 +190,16 @@ struct LaunchCfg {
     uint32_t lds_bytes;   // dynamic LDS per workgroup
     bool swar;            // AC: byte classes computed in registers
     uint32_t ilp;         // virtual lanes per thread (1 or 2)
+    uint32_t csr_lds;     // LDS byte offset of the id CSR (0: global memory)
 };
+// csr_in_lds: single-text scans may copy the id CSR to LDS (batched launches
+// keep it in global memory).
 mpm_status resolve_variant(const mpm_index *idx, const mpm_variant *v, uint64_t ntiles_hint,
-                           LaunchCfg *cfg);
+                           LaunchCfg *cfg, bool csr_in_lds = false);
+// Words of the id CSR arrays: uoff (d_unique + 1) and ids (d), each padded
+// to 16 bytes.
+uint32_t csr_uoff_words(const mpm_index *idx);
+uint32_t csr_uids_words(const mpm_index *idx);
 uint64_t tile_bytes(const LaunchCfg &cfg);
 mpm_status launch_scan(const mpm_index *idx, const LaunchCfg &cfg, const ScanDev &sd,
                        void *stream);

@@ -87,6 +87,7 @@ AcDev ac_dev(const mpm_index *ix)
     a.m = ix->m;
     a.dfa_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
+    a.n_single = ix->n_single;
     a.swar_ok = ix->swar_ok;
     a.swar_shift = ix->swar_shift;
     uint32_t w[4];
@@ -117,6 +118,7 @@ WmDev wm_dev(const mpm_index *ix)
     a.key_len = ix->key_len;
     a.table_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
+    a.n_single = ix->n_single;
     return a;
 }
 
@@ -135,8 +137,11 @@ uint64_t tile_bytes(const LaunchCfg &cfg)
     return (uint64_t)cfg.lane_bytes * cfg.block_threads * cfg.ilp;
 }
 
+uint32_t csr_uoff_words(const mpm_index *ix) { return (ix->du + 1 + 3) / 4 * 4; }
+uint32_t csr_uids_words(const mpm_index *ix) { return (ix->d + 3) / 4 * 4; }
+
 mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t ntiles,
-                           LaunchCfg *cfg)
+                           LaunchCfg *cfg, bool csr_in_lds)
 {
     mpm_variant d = {0, 0, 0, 0, 0};
     if (v)
@@ -167,6 +172,19 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     cfg->swar = ix->algo == MPM_ALGO_AC && ix->swar_ok && !(d.flags & MPM_VARIANT_NO_SWAR);
     cfg->ilp = (ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2)) ? 2 : 1;
     cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS ? (uint32_t)ix->table_bytes : 0u);
+    cfg->csr_lds = 0;
+    if (csr_in_lds) {
+        // Every reported occurrence reads the id CSR (the ids of its string,
+        // and their count when strings repeat): served from LDS when it fits
+        // without costing a workgroup slot per CU.
+        const uint64_t csr = 4ull * (csr_uoff_words(ix) + csr_uids_words(ix));
+        const uint64_t with = cfg->lds_bytes + csr;
+        if (with <= (uint64_t)lim.max_lds &&
+            (uint64_t)lim.max_lds / with == (uint64_t)lim.max_lds / cfg->lds_bytes) {
+            cfg->csr_lds = cfg->lds_bytes;
+            cfg->lds_bytes = (uint32_t)with;
+        }
+    }
     cfg->grid = 0;
     if (ntiles) {
         const void *k = kernel_for(ix, *cfg);

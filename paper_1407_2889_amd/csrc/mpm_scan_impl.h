@@ -47,6 +47,7 @@ template <typename T> using lds_cptr = const LDS_AS T *;
 template <typename T> using glb_cptr = const GLB_AS T *;
 template <bool InLds, typename T> struct TabPtr { using type = glb_cptr<T>; };
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte load/store unit
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));  // two 16-bit states
 template <typename T> struct TabPtr<true, T> { using type = lds_cptr<T>; };
 
 static const int K_SLOTS = 4;  // occurrences a lane keeps in registers
@@ -245,21 +246,45 @@ __device__ __forceinline__ void chunk_offsets(const uint32_t (&cnt)[I], uint64_t
 
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
+// The distinct-string -> id CSR (uoff, ids), read from LDS when the launch
+// copied it there (nonzero byte offsets) and from global memory otherwise.
+struct IdMap {
+    glb_cptr<uint32_t> uoff, uids;
+    uint32_t lds_uoff, lds_uids;
+    uint32_t dupfree;
+    uint32_t n_single;  // strings below this have one id: no CSR read to count
+
+    __device__ __forceinline__ uint32_t off(uint32_t u) const
+    {
+        return lds_uoff ? lds_at<const uint32_t>(lds_uoff)[u] : uoff[u];
+    }
+    __device__ __forceinline__ uint32_t id(uint32_t j) const
+    {
+        return lds_uids ? lds_at<const uint32_t>(lds_uids)[j] : uids[j];
+    }
+    // ids reported for one occurrence of distinct string u
+    __device__ __forceinline__ uint32_t count(uint32_t u) const
+    {
+        if (u < n_single)
+            return 1u;
+        return off(u + 1) - off(u);
+    }
+};
+
 __device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_t &ob, uint32_t pos,
-                                          uint32_t u, const GLB_AS uint32_t *uoff,
-                                          const GLB_AS uint32_t *uids, uint32_t dupfree)
+                                          uint32_t u, const IdMap &im)
 {
     GLB_AS v2u *out = (GLB_AS v2u *)out_;
-    if (dupfree) {
+    if (im.dupfree) {
         if (ob < cap)
-            out[ob] = v2u{pos, uids[u]};
+            out[ob] = v2u{pos, im.id(u)};
         ++ob;
         return;
     }
-    const uint32_t b = uoff[u], e = uoff[u + 1];
+    const uint32_t b = im.off(u), e = im.off(u + 1);
     for (uint32_t j = b; j < e; ++j) {
         if (ob < cap)
-            out[ob] = v2u{pos, uids[j]};
+            out[ob] = v2u{pos, im.id(j)};
         ++ob;
     }
 }
@@ -653,27 +678,60 @@ struct AcWalk {
         for (uint32_t l = 0; l < nl; ++l) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                uint32_t s0[I], mx[I];
+                if constexpr (I == 1) {
+                    // The piece's 16 states, packed in pairs of 16 bits (the
+                    // table has fewer than 2^16 states), with their running
+                    // maximum per half: a piece that reached a terminal state
+                    // is reported from these, without walking it again
+                    // (which would cost the whole wave a second chain of
+                    // lookups whenever any of its lanes had a hit).
+                    u16x2 pk[8];
+                    u16x2 mxp = {0, 0};
+                    uint32_t prev = 0;
 #pragma unroll
-                for (int c = 0; c < I; ++c) {
-                    s0[c] = s[c];
-                    mx[c] = 0;
-                }
+                    for (int k = 0; k < 16; ++k) {
+                        s[0] = next(s[0], col_nib(cur[0][2 * j], cur[0][2 * j + 1], k));
+                        if (k & 1) {
+                            // low halves of both states (they are below 2^16)
+                            pk[k >> 1] = __builtin_bit_cast(
+                                u16x2, __builtin_amdgcn_perm(s[0], prev, 0x05040100u));
+                            mxp = __builtin_elementwise_max(mxp, pk[k >> 1]);
+                        } else {
+                            prev = s[0];
+                        }
+                    }
+                    if ((uint32_t)max(mxp.x, mxp.y) >= first_term) {
+                        const uint64_t q = p[0] + ((uint64_t)l << 7) + 16 * j;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
+                        for (int k = 0; k < 16; ++k) {
+                            const uint32_t st = (k & 1) ? pk[k >> 1].y : pk[k >> 1].x;
+                            if (st >= first_term)
+                                cb(0, q + k + 1 - m, st - first_term);
+                        }
+                    }
+                } else {
+                    uint32_t s0[I], mx[I];
 #pragma unroll
                     for (int c = 0; c < I; ++c) {
-                        s[c] = next(s[c], col_nib(cur[c][2 * j], cur[c][2 * j + 1], k));
-                        mx[c] = max(mx[c], s[c]);
+                        s0[c] = s[c];
+                        mx[c] = 0;
                     }
-                }
 #pragma unroll
-                for (int c = 0; c < I; ++c) {
-                    if (mx[c] >= first_term) {
-                        auto one = [&](uint64_t st, uint32_t u) { cb(c, st, u); };
-                        uint32_t st = opaque(s0[c]);
-                        report_nib(st, cur[c][2 * j], cur[c][2 * j + 1], 16,
-                                   p[c] + ((uint64_t)l << 7) + 16 * j, one);
+                    for (int k = 0; k < 16; ++k) {
+#pragma unroll
+                        for (int c = 0; c < I; ++c) {
+                            s[c] = next(s[c], col_nib(cur[c][2 * j], cur[c][2 * j + 1], k));
+                            mx[c] = max(mx[c], s[c]);
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < I; ++c) {
+                        if (mx[c] >= first_term) {
+                            auto one = [&](uint64_t st, uint32_t u) { cb(c, st, u); };
+                            uint32_t st = opaque(s0[c]);
+                            report_nib(st, cur[c][2 * j], cur[c][2 * j + 1], 16,
+                                       p[c] + ((uint64_t)l << 7) + 16 * j, one);
+                        }
                     }
                 }
             }
@@ -1024,8 +1082,7 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
                                               mpm_match *out, uint64_t cap, uint64_t *total,
                                               uint64_t first_g, uint64_t nt, uint64_t g,
                                               uint32_t L, uint32_t m, uint32_t epoch,
-                                              glb_cptr<uint32_t> uoff, glb_cptr<uint32_t> uids,
-                                              uint32_t dupfree, uint32_t *hdr, uint64_t *status,
+                                              const IdMap &im, uint32_t *hdr, uint64_t *status,
                                               uint64_t *s_scan)
 {
     constexpr int I = Walk::ILP;
@@ -1059,14 +1116,16 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
         }
     }
     auto rec0 = [&](uint64_t start, uint32_t u) {
+        if (nu[0] < (uint32_t)KS) {
 #pragma unroll
-        for (int k = 0; k < KS; ++k)
-            if (nu[0] == (uint32_t)k) {
-                so[0][k] = (uint32_t)start;
-                su[0][k] = u;
-            }
+            for (int k = 0; k < KS; ++k)
+                if (nu[0] == (uint32_t)k) {
+                    so[0][k] = (uint32_t)start;
+                    su[0][k] = u;
+                }
+        }
         ++nu[0];
-        nid[0] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
+        nid[0] += im.count(u);
     };
     if constexpr (I == 1) {
         wk.lane(text, n, base, lo[0], hi[0], rec0);
@@ -1079,7 +1138,7 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
                     su[I - 1][k] = u;
                 }
             ++nu[I - 1];
-            nid[I - 1] += dupfree ? 1u : (uoff[u + 1] - uoff[u]);
+            nid[I - 1] += im.count(u);
         };
         wk.lane2(text, n, base, lo[0], hi[0], lo[I - 1], hi[I - 1], rec0, rec1);
     }
@@ -1099,10 +1158,10 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
 #pragma unroll
             for (int k = 0; k < KS; ++k)
                 if ((uint32_t)k < nu[v])
-                    write_ids(out, cap, o, so[v][k], su[v][k], uoff, uids, dupfree);
+                    write_ids(out, cap, o, so[v][k], su[v][k], im);
         } else {
             wk.lane_again(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
-                write_ids(out, cap, o, (uint32_t)start, u, uoff, uids, dupfree);
+                write_ids(out, cap, o, (uint32_t)start, u, im);
             });
         }
     }
@@ -1152,9 +1211,18 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     uint32_t *const hdr = sd.hdr;
     uint64_t *const status = sd.status;
     const TextDesc *const multi = sd.multi;
-    glb_cptr<uint32_t> uoff = (glb_cptr<uint32_t>)uoff_;
-    glb_cptr<uint32_t> uids = (glb_cptr<uint32_t>)uids_;
+    IdMap im;
+    im.uoff = (glb_cptr<uint32_t>)uoff_;
+    im.uids = (glb_cptr<uint32_t>)uids_;
+    im.lds_uoff = sd.csr_uoff_lds;
+    im.lds_uids = sd.csr_uids_lds;
+    im.dupfree = dupfree;
+    im.n_single = a.n_single;
     const uint32_t m = a.m;
+    if (im.lds_uoff) {  // the id CSR into LDS (synchronised by the setup below)
+        copy_to_lds<W>(im.lds_uoff, (const uint8_t *)uoff_, 4 * sd.csr_uoff_words);
+        copy_to_lds<W>(im.lds_uids, (const uint8_t *)uids_, 4 * sd.csr_uids_words);
+    }
 
     Walk wk;
     wk.template setup<W>(a, unused);
@@ -1186,8 +1254,8 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
         if (g >= ntiles)
             break;
         process_chunk<Walk, W>(wk, (glb_cptr<uint8_t>)s_td.text, s_td.n, s_td.out, s_td.cap,
-                               s_td.total, s_td.tile_begin, s_td.ntiles, g, L, m, s_epoch, uoff,
-                               uids, dupfree, hdr, status, s_scan);
+                               s_td.total, s_td.tile_begin, s_td.ntiles, g, L, m, s_epoch, im,
+                               hdr, status, s_scan);
         __syncthreads();
     }
     finish_launch(hdr, s_epoch);
@@ -1208,8 +1276,14 @@ __device__ __forceinline__ void batch_chunk(const Dev &dev, glb_cptr<uint8_t> te
 {
     Walk wk;
     wk.bind(dev);
-    process_chunk<Walk, W>(wk, text, n, out, cap, total, first_g, nt, g, L, dev.m, epoch,
-                           (glb_cptr<uint32_t>)dev.uoff, (glb_cptr<uint32_t>)dev.uids, dev.dupfree,
+    IdMap im;
+    im.uoff = (glb_cptr<uint32_t>)dev.uoff;
+    im.uids = (glb_cptr<uint32_t>)dev.uids;
+    im.lds_uoff = 0;
+    im.lds_uids = 0;
+    im.dupfree = dev.dupfree;
+    im.n_single = dev.n_single;
+    process_chunk<Walk, W>(wk, text, n, out, cap, total, first_g, nt, g, L, dev.m, epoch, im,
                            hdr, status, s_scan);
 }
 

@@ -121,8 +121,10 @@ def test_unique_csr():
     P = np.frombuffer(b"CCAAGGAACC", np.uint8).reshape(5, 2)   # CC AA GG AA CC
     ix = mpm.build_ac(P)
     uoff, ids = ix.export_unique()
-    assert uoff.tolist() == [0, 2, 4, 5]      # AA:{1,3} CC:{0,4} GG:{2}
-    assert ids.tolist() == [1, 3, 0, 4, 2]
+    # strings with one id first, then repeated ones, each in string order:
+    # GG:{2} AA:{1,3} CC:{0,4}
+    assert uoff.tolist() == [0, 1, 3, 5]
+    assert ids.tolist() == [2, 1, 3, 0, 4]
     assert ix.info()["max_dup"] == 2
 
 
