@@ -182,7 +182,8 @@ class Selector:
         return sel
 
     def predict_ms(self, feats: np.ndarray) -> np.ndarray:
-        return np.exp(self.timing.predict(feats))
+        # log-milliseconds clipped to a sane range before exponentiating
+        return np.exp(np.clip(self.timing.predict(feats), -30.0, 30.0))
 
     def predict_gbps(self, feats: np.ndarray, n: np.ndarray) -> np.ndarray:
         return np.asarray(n, np.float64)[:, None] / (self.predict_ms(feats) * 1e-3) / 1e9
@@ -195,7 +196,9 @@ class Selector:
         order = np.argsort(score, axis=1)
         r = np.arange(len(order))
         best = order[:, 0]
-        gap = np.exp(score[r, order[:, 1]] - score[r, best]) - 1.0
+        # a runner-up that cannot run (score inf) leaves an infinite gap
+        diff = np.minimum(score[r, order[:, 1]] - score[r, best], 30.0)
+        gap = np.exp(diff) - 1.0
         return best, gap < margin
 
     def save(self, path: str):
