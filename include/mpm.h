@@ -72,9 +72,16 @@ typedef struct {
     uint32_t reserved[7];
 } mpm_opts;
 
-#define MPM_PLACE_AUTO 0    /* LDS when the tables fit beside the scan's own LDS use, else global */
+#define MPM_PLACE_AUTO 0    /* LDS when the tables fit beside the scan's own LDS use, else
+                               MPM_PLACE_HOT when the index has a hot part, else global */
 #define MPM_PLACE_LDS 1     /* matching tables copied into LDS once per workgroup */
 #define MPM_PLACE_GLOBAL 2  /* matching tables read through the L2/L1 caches */
+#define MPM_PLACE_HOT 3     /* the part of the tables read on nearly every step in LDS, the
+                               rest through the caches: Aho-Corasick tables with 16-bit
+                               entries keep their first rows in breadth-first order (the
+                               shallow states a walk over text visits), Wu-Manber keeps
+                               SHIFT and leaves the buckets global. Other indexes:
+                               EUNSUPPORTED */
 
 /* Launch variant of a scan. Zero fields take defaults. The text is split
  * into chunks of lane_bytes * block_threads starting positions; each lane owns

@@ -38,7 +38,7 @@ _L = C.CDLL(LIB_PATH)
 MPM_OK, MPM_EINVAL, MPM_EOVERFLOW, MPM_ENOMEM, MPM_EHIP, MPM_ETOOBIG, MPM_EUNSUPPORTED, MPM_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 ALGO_AC, ALGO_WM = 1, 2
-PLACE_AUTO, PLACE_LDS, PLACE_GLOBAL = 0, 1, 2
+PLACE_AUTO, PLACE_LDS, PLACE_GLOBAL, PLACE_HOT = 0, 1, 2, 3
 
 _STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOVERFLOW", -3: "ENOMEM", -4: "EHIP",
                  -5: "ETOOBIG", -6: "EUNSUPPORTED", -7: "ESTATE"}

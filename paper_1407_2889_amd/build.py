@@ -15,7 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmpm.so")
 SOURCES = ["mpm_host.cpp", "mpm_scan.hip", "mpm_scan_ac16_lds.hip", "mpm_scan_ac16_glb.hip",
-           "mpm_scan_ac32_glb.hip", "mpm_scan_wm.hip", "mpm_scan_batch.hip", "mpm_mlp.hip"]
+           "mpm_scan_ac16_hot.hip", "mpm_scan_ac32_glb.hip", "mpm_scan_wm.hip",
+           "mpm_scan_batch_ac16_lds.hip", "mpm_scan_batch_ac16_glb.hip",
+           "mpm_scan_batch_ac16_hot.hip", "mpm_scan_batch_other.hip", "mpm_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -733,6 +733,7 @@ struct mpm_batch {
     // One persistent launch per block size; its texts ordered by index and
     // walker kind so that LDS tables are reused across consecutive chunks.
     struct Group {
+        uint32_t kind = 0;  // walker kind of the launch (BK_*)
         uint32_t W = 0;
         uint32_t grid_req = 0;
         uint32_t grid = 0;
@@ -775,13 +776,14 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             float hint;
             float group_hint;
         };
-        // Launch key: block size and LDS class. A launch's LDS size is the
-        // largest its texts need, so texts with small tables are kept apart
-        // from texts whose tables limit a CU to one or two workgroups.
+        // Launch key: walker kind, block size and LDS class. Each launch runs
+        // one kernel (one walker kind); its LDS size is the largest its texts
+        // need, so texts with small tables are kept apart from texts whose
+        // tables limit a CU to one or two workgroups.
         auto lds_class = [](uint32_t lds) -> uint32_t {
             return lds <= 8192 ? 0 : lds <= 32768 ? 1 : lds <= 65536 ? 2 : 3;
         };
-        std::map<std::pair<uint32_t, uint32_t>, std::vector<Item>> byw;
+        std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<Item>> byw;
         for (uint32_t k = 0; k < count; k++) {
             const mpm_request &r = reqs[k];
             if (!r.idx || !r.d_total || (r.n && !r.d_text) || (r.capacity && !r.d_out)) {
@@ -818,7 +820,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return fail(MPM_EUNSUPPORTED, "mpm_batch_plan: too many copies of one pattern");
             }
             it.kind = batch_kind(r.idx, it.cfg);
-            const auto key = std::make_pair(it.cfg.block_threads, lds_class(it.cfg.lds_bytes));
+            const auto key = std::make_tuple(it.kind, it.cfg.block_threads, lds_class(it.cfg.lds_bytes));
             byw[key].push_back(it);
             if (r.variant.grid)
                 byw[key].back().cfg.grid = r.variant.grid;
@@ -844,7 +846,8 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return x.hint > y.hint;
             });
             mpm_batch::Group g;
-            g.W = kv.first.first;
+            g.kind = std::get<0>(kv.first);
+            g.W = std::get<1>(kv.first);
             std::map<const mpm_index *, uint32_t> slot;
             for (const Item &it : items) {
                 const mpm_request &r = reqs[it.req];
@@ -881,7 +884,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
         }
         uint64_t off = 0;
         for (auto &g : b->groups) {
-            g.grid = batch_grid(g.W, g.lds, g.ntiles, g.grid_req);
+            g.grid = batch_grid(g.kind, g.W, g.lds, g.ntiles, g.grid_req);
             g.text_off = off;
             off = align_up(off + g.texts.size() * sizeof(BatchText), 256);
             g.idx_off = off;
@@ -980,7 +983,7 @@ mpm_status mpm_batch_run(const mpm_batch *cb, void *stream)
         bd.ntiles = g.ntiles;
         bd.hdr = (uint32_t *)(b->d_buf + g.work_off);
         bd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
-        mpm_status st = launch_batch(bd, g.W, g.grid, g.lds, ls);
+        mpm_status st = launch_batch(bd, g.kind, g.W, g.grid, g.lds, ls);
         if (st)
             return st;
         if (fan && (hipEventRecord(b->done[gi], (hipStream_t)ls) != hipSuccess ||
@@ -1123,16 +1126,17 @@ mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n
         bd.ntiles = ntiles;
         bd.hdr = (uint32_t *)((uint8_t *)d_work + wo);
         bd.status = (uint64_t *)((uint8_t *)d_work + wo + WS_HEADER_BYTES);
-        const uint32_t grid = batch_grid(cfg.block_threads, cfg.lds_bytes, ntiles,
+        const uint32_t kind = batch_kind(idx, cfg);
+        const uint32_t grid = batch_grid(kind, cfg.block_threads, cfg.lds_bytes, ntiles,
                                          v ? v->grid : 0);
         hipEvent_t a, z;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&z) != hipSuccess)
             return fail(MPM_EHIP, "mpm_tune_time: event creation failed");
         // warm-up, then `reps` launches between two events: the mean launch
-        st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);
+        st = launch_batch(bd, kind, cfg.block_threads, grid, cfg.lds_bytes, stream);
         (void)hipEventRecord(a, s);
         for (uint32_t r = 0; r < reps && st == MPM_OK; r++)
-            st = launch_batch(bd, cfg.block_threads, grid, cfg.lds_bytes, stream);
+            st = launch_batch(bd, kind, cfg.block_threads, grid, cfg.lds_bytes, stream);
         (void)hipEventRecord(z, s);
         float ms = 0.f;
         if (st == MPM_OK && hipEventSynchronize(z) == hipSuccess)

@@ -33,6 +33,8 @@ struct AcDev {
     uint32_t dfa_bytes;     // bytes of the table (multiple of 16)
     uint32_t dupfree;       // every distinct string has exactly one id
     uint32_t n_single;      // distinct strings below this have one id each
+    uint32_t hot_states;    // hot placement: rows [0, hot_states) in LDS
+    uint32_t hot_bytes;     // bytes of those rows (multiple of 16)
     // Byte classes without a lookup table, usable when the pattern bytes
     // have distinct 3-bit codes (b >> swar_shift) & 7: perm_byte selects, per
     // code, the only byte with that code that is a pattern byte (or a byte
@@ -64,6 +66,7 @@ struct WmDev {
     uint32_t table_bytes;
     uint32_t dupfree;
     uint32_t n_single;
+    uint32_t shift_bytes;   // bytes of SHIFT at the start of `tables` (multiple of 16)
 };
 
 // One text of a launch. Tiles of a launch are numbered globally; a text
@@ -109,6 +112,8 @@ enum {
     BK_AC32_GLB = 2,
     BK_WM_LDS = 3,
     BK_WM_GLB = 4,
+    BK_AC16_HOT = 5,
+    BK_WM_HOT = 6,
     BK_WALK_MASK = 0x7f,
     BK_SWAR = 0x80
 };
@@ -208,6 +213,9 @@ mpm_status launch_zero_totals(uint64_t *const *d_totals_dev, uint32_t count, uin
 AcDev ac_dev(const mpm_index *ix);
 WmDev wm_dev(const mpm_index *ix);
 uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c);
-uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t grid_req);
-mpm_status launch_batch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds, void *stream);
+// Batched launches run one kernel per walker kind (BK_*, with BK_SWAR).
+uint32_t batch_grid(uint32_t kind, uint32_t W, uint32_t lds_bytes, uint64_t ntiles,
+                    uint32_t grid_req);
+mpm_status launch_batch(const BatchDev &bd, uint32_t kind, uint32_t W, uint32_t grid, uint32_t lds,
+                        void *stream);
 }  // namespace mpm

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "mpm_scan_impl.h"
@@ -12,6 +13,8 @@ namespace mpm {
 
 const void *ac16_lds_kernel(const LaunchCfg &c);
 const void *ac16_glb_kernel(const LaunchCfg &c);
+const void *ac16_hot_kernel(const LaunchCfg &c);
+hipError_t ac16_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 const void *ac32_glb_kernel(const LaunchCfg &c);
 hipError_t ac16_lds_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 hipError_t ac16_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
@@ -99,6 +102,12 @@ AcDev ac_dev(const mpm_index *ix)
     a.perm_byte_hi = w[1];
     a.perm_col_lo = w[2];
     a.perm_col_hi = w[3];
+    // hot placement: as many whole rows as the LDS holds beside the fixed
+    // regions (16-byte multiple)
+    const uint64_t budget = ((uint64_t)limits().max_lds - 1024u) & ~15ull;
+    const uint64_t hb = std::min<uint64_t>(budget, ix->table_bytes);
+    a.hot_bytes = (uint32_t)hb;
+    a.hot_states = (uint32_t)(hb / ((uint64_t)a.cp * ix->state_bytes));
     return a;
 }
 
@@ -119,7 +128,22 @@ WmDev wm_dev(const mpm_index *ix)
     a.table_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
     a.n_single = ix->n_single;
+    a.shift_bytes = (uint32_t)(((uint64_t)ix->shift16.size() * 2 + 15) / 16 * 16);
     return a;
+}
+
+// Whether an index can run with the hot part of its tables in LDS.
+static bool has_hot(const mpm_index *ix)
+{
+    return ix->algo == MPM_ALGO_WM || (ix->algo == MPM_ALGO_AC && ix->state_bytes == 2);
+}
+
+// LDS bytes of the hot part.
+static uint64_t hot_lds_bytes(const mpm_index *ix)
+{
+    if (ix->algo == MPM_ALGO_AC)
+        return ac_dev(ix).hot_bytes;
+    return ((uint64_t)ix->shift16.size() * 2 + 15) / 16 * 16;
 }
 
 static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
@@ -127,6 +151,8 @@ static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
     if (ix->algo == MPM_ALGO_AC) {
         if (ix->state_bytes == 4)
             return ac32_glb_kernel(c);  // tables of 2^16 states or more never fit in LDS
+        if (c.placement == MPM_PLACE_HOT)
+            return ac16_hot_kernel(c);
         return c.placement == MPM_PLACE_LDS ? ac16_lds_kernel(c) : ac16_glb_kernel(c);
     }
     return wm_kernel(c);
@@ -152,7 +178,7 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
         return fail(MPM_EINVAL, "variant: lane_bytes=%u must be a multiple of 16 in 16..4096", L);
     if (W != 256 && W != 512 && W != 1024)
         return fail(MPM_EINVAL, "variant: block_threads=%u must be 256, 512 or 1024", W);
-    if (d.placement > MPM_PLACE_GLOBAL)
+    if (d.placement > MPM_PLACE_HOT)
         return fail(MPM_EINVAL, "variant: unknown placement %u", d.placement);
     const DeviceLimits lim = limits();
     // dynamic LDS: the kernels' fixed header and byte-class regions, then the
@@ -160,18 +186,25 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     const uint32_t fixed = 1024u;
     const uint64_t table_lds = fixed + ix->table_bytes;
     const bool fits = table_lds <= (uint64_t)lim.max_lds;
+    const bool ilp2 = ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2);
+    const bool hot_ok = has_hot(ix) && !ilp2;
     uint32_t place = d.placement;
     if (place == MPM_PLACE_AUTO)
-        place = fits ? MPM_PLACE_LDS : MPM_PLACE_GLOBAL;
+        place = fits ? MPM_PLACE_LDS : (hot_ok ? MPM_PLACE_HOT : MPM_PLACE_GLOBAL);
     if (place == MPM_PLACE_LDS && !fits)
         return fail(MPM_EUNSUPPORTED, "variant: tables of %llu bytes do not fit in LDS",
                     (unsigned long long)ix->table_bytes);
+    if (place == MPM_PLACE_HOT && !hot_ok)
+        return fail(MPM_EUNSUPPORTED, "variant: this index (or the two-chain variant) has no "
+                    "hot placement");
     cfg->lane_bytes = L;
     cfg->block_threads = W;
     cfg->placement = place;
     cfg->swar = ix->algo == MPM_ALGO_AC && ix->swar_ok && !(d.flags & MPM_VARIANT_NO_SWAR);
     cfg->ilp = (ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2)) ? 2 : 1;
-    cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS ? (uint32_t)ix->table_bytes : 0u);
+    cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS   ? (uint32_t)ix->table_bytes
+                              : place == MPM_PLACE_HOT ? (uint32_t)hot_lds_bytes(ix)
+                                                       : 0u);
     cfg->csr_lds = 0;
     if (csr_in_lds) {
         // Every reported occurrence reads the id CSR (the ids of its string,
@@ -217,6 +250,8 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
         const AcDev a = ac_dev(ix);
         if (ix->state_bytes == 4)
             e = ac32_glb_launch(a, c, sd, s);
+        else if (c.placement == MPM_PLACE_HOT)
+            e = ac16_hot_launch(a, c, sd, s);
         else
             e = c.placement == MPM_PLACE_LDS ? ac16_lds_launch(a, c, sd, s) : ac16_glb_launch(a, c, sd, s);
     } else {
@@ -231,17 +266,33 @@ uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c)
 {
     uint32_t k;
     if (ix->algo == MPM_ALGO_AC)
-        k = ix->state_bytes == 4 ? BK_AC32_GLB
-                                 : (c.placement == MPM_PLACE_LDS ? BK_AC16_LDS : BK_AC16_GLB);
+        k = ix->state_bytes == 4               ? BK_AC32_GLB
+            : c.placement == MPM_PLACE_LDS     ? BK_AC16_LDS
+            : c.placement == MPM_PLACE_HOT     ? BK_AC16_HOT
+                                               : BK_AC16_GLB;
     else
-        k = c.placement == MPM_PLACE_LDS ? BK_WM_LDS : BK_WM_GLB;
+        k = c.placement == MPM_PLACE_LDS   ? BK_WM_LDS
+            : c.placement == MPM_PLACE_HOT ? BK_WM_HOT
+                                           : BK_WM_GLB;
     return k | (c.swar ? (uint32_t)BK_SWAR : 0u);
 }
 
-uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t grid_req)
+static const void *batch_kernel_ptr(uint32_t kind, uint32_t W)
+{
+    const bool swar = (kind & BK_SWAR) != 0;
+    switch (kind & BK_WALK_MASK) {
+    case BK_AC16_LDS: return batch_kernel_ac16<PL_LDS>(swar, W);
+    case BK_AC16_GLB: return batch_kernel_ac16<PL_GLB>(swar, W);
+    case BK_AC16_HOT: return batch_kernel_ac16<PL_HOT>(swar, W);
+    }
+    return batch_kernel_other(kind, W);
+}
+
+uint32_t batch_grid(uint32_t kind, uint32_t W, uint32_t lds_bytes, uint64_t ntiles,
+                    uint32_t grid_req)
 {
     const DeviceLimits lim = limits();
-    const void *k = batch_kernel_ptr(W);
+    const void *k = batch_kernel_ptr(kind, W);
     if (lds_bytes > 65536)
         (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     int nb = 0;
@@ -254,11 +305,21 @@ uint32_t batch_grid(uint32_t W, uint32_t lds_bytes, uint64_t ntiles, uint32_t gr
     return (uint32_t)(grid < 1 ? 1 : grid);
 }
 
-mpm_status launch_batch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds, void *stream)
+mpm_status launch_batch(const BatchDev &bd, uint32_t kind, uint32_t W, uint32_t grid, uint32_t lds,
+                        void *stream)
 {
     if (lds > 65536)
-        (void)hipFuncSetAttribute(batch_kernel_ptr(W), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipError_t e = batch_launch(bd, W, grid, lds, (hipStream_t)stream);
+        (void)hipFuncSetAttribute(batch_kernel_ptr(kind, W), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+    hipError_t e;
+    const bool swar = (kind & BK_SWAR) != 0;
+    hipStream_t s = (hipStream_t)stream;
+    switch (kind & BK_WALK_MASK) {
+    case BK_AC16_LDS: e = batch_launch_ac16<PL_LDS>(bd, swar, W, grid, lds, s); break;
+    case BK_AC16_GLB: e = batch_launch_ac16<PL_GLB>(bd, swar, W, grid, lds, s); break;
+    case BK_AC16_HOT: e = batch_launch_ac16<PL_HOT>(bd, swar, W, grid, lds, s); break;
+    default: e = batch_launch_other(bd, kind, W, grid, lds, s); break;
+    }
     if (e != hipSuccess)
         return fail(MPM_EHIP, "batch launch: %s", hipGetErrorString(e));
     return MPM_OK;

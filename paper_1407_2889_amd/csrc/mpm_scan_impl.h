@@ -35,6 +35,8 @@
 
 #include <string.h>
 
+#include <type_traits>
+
 #include "mpm_internal.h"
 
 namespace mpm {
@@ -46,6 +48,9 @@ namespace mpm {
 template <typename T> using lds_cptr = const LDS_AS T *;
 template <typename T> using glb_cptr = const GLB_AS T *;
 template <bool InLds, typename T> struct TabPtr { using type = glb_cptr<T>; };
+// Table placements of the walkers: global memory, wholly in LDS, or the hot
+// part in LDS and the rest in global memory.
+enum { PL_GLB = 0, PL_LDS = 1, PL_HOT = 2 };
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte load/store unit
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));  // two 16-bit states
 template <typename T> struct TabPtr<true, T> { using type = lds_cptr<T>; };
@@ -398,13 +403,18 @@ __device__ __forceinline__ uint32_t swar_cols(uint32_t w, uint32_t sh, uint32_t 
     return col & ~(nz | (nz - (nz >> 7)));  // 0xFF in every byte != 0
 }
 
-template <typename St, bool InLds, bool Swar, int Ilp>
+template <typename St, int P, bool Swar, int Ilp>
 struct AcWalk {
     using Dev = AcDev;
     static constexpr int ILP = Ilp;
+    static constexpr bool InLds = P == PL_LDS;
+    // PL_HOT: states below hot (the first rows in breadth-first order, where
+    // a walk over text spends nearly all its steps) are read from LDS, the
+    // others from global memory.
+    static constexpr bool Hot = P == PL_HOT;
     typename TabPtr<InLds, uint8_t>::type dfab;  // table, addressed in bytes
     lds_cptr<uint16_t> cls;                      // column byte offset per byte value
-    uint32_t rowb, first_term, m, sh, pb_lo, pb_hi, pc_lo, pc_hi;
+    uint32_t rowb, first_term, m, sh, pb_lo, pb_hi, pc_lo, pc_hi, hot;
 
     // Copy what this walker reads from LDS (no barrier).
     template <int W>
@@ -413,6 +423,8 @@ struct AcWalk {
         copy_to_lds<W>(LDS_CLS_OFF, a.cls, 512);
         if (InLds)
             copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.dfa_bytes);
+        if (Hot)
+            copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.hot_bytes);
     }
 
     __device__ __forceinline__ void bind(const AcDev &a)
@@ -435,6 +447,7 @@ struct AcWalk {
             dfab = lds_at<const uint8_t>(LDS_TAB_OFF);
         else
             dfab = (glb_cptr<uint8_t>)a.dfa;
+        hot = a.hot_states;
     }
 
     template <int W>
@@ -449,6 +462,10 @@ struct AcWalk {
     __device__ __forceinline__ uint32_t next(uint32_t s, uint32_t coloff) const
     {
         const uint32_t off = sizeof(St) == 2 ? __umul24(s, rowb) + coloff : s * rowb + coloff;
+        if constexpr (Hot) {
+            if (s < hot)
+                return *(lds_cptr<St>)(lds_at<const uint8_t>(LDS_TAB_OFF) + off);
+        }
         return *(typename TabPtr<InLds, St>::type)(dfab + off);
     }
 
@@ -914,11 +931,15 @@ __device__ __forceinline__ uint32_t codes4(uint32_t w, uint32_t sh)
     return (x | (x >> 12)) & 0xFFu;
 }
 
-template <bool InLds>
+template <int P>
 struct WmWalk {
     using Dev = WmDev;
     static constexpr int ILP = 1;
-    typename TabPtr<InLds, uint16_t>::type sh16;
+    static constexpr bool InLds = P == PL_LDS;
+    // PL_HOT: SHIFT (read for every window) in LDS, the buckets (read only
+    // for windows with a zero shift) in global memory.
+    static constexpr bool Hot = P == PL_HOT;
+    typename TabPtr<InLds || Hot, uint16_t>::type sh16;
     typename TabPtr<InLds, uint32_t>::type boff, bkey, bu;
     glb_cptr<uint8_t> pats;
     uint32_t m, B, csh, kl, hmask, kmask;
@@ -929,6 +950,8 @@ struct WmWalk {
     {
         if (InLds)
             copy_to_lds<W>(LDS_TAB_OFF, a.tables, a.table_bytes);
+        if (Hot)
+            copy_to_lds<W>(LDS_TAB_OFF, a.tables, a.shift_bytes);
     }
 
     __device__ __forceinline__ void bind(const WmDev &a)
@@ -944,7 +967,10 @@ struct WmWalk {
             base = lds_at<const uint8_t>(LDS_TAB_OFF);
         else
             base = (glb_cptr<uint8_t>)a.tables;
-        sh16 = (typename TabPtr<InLds, uint16_t>::type)base;
+        if constexpr (Hot)
+            sh16 = lds_at<const uint16_t>(LDS_TAB_OFF);
+        else
+            sh16 = (typename TabPtr<InLds, uint16_t>::type)base;
         boff = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_boff);
         bkey = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bkey);
         bu = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bu);
@@ -1020,8 +1046,8 @@ struct WmWalk {
             while (nx < e) {
                 const uint32_t o2 = c2 + 2u * (nx - e);
                 const uint32_t hb = (uint32_t)(h >> o2) & hmask2;
-                const uint32_t sv = *(typename TabPtr<InLds, uint16_t>::type)(
-                    (typename TabPtr<InLds, uint8_t>::type)sh16 + hb);
+                const uint32_t sv = *(typename TabPtr<InLds || Hot, uint16_t>::type)(
+                    (typename TabPtr<InLds || Hot, uint8_t>::type)sh16 + hb);
                 if (sv & 0x8000u) {
                     const uint32_t b = sv & 0x7fffu;
                     const uint32_t key = kl ? ((uint32_t)(h >> (o2 - kdrop)) & kmask) : 0u;
@@ -1287,7 +1313,18 @@ __device__ __forceinline__ void batch_chunk(const Dev &dev, glb_cptr<uint8_t> te
                            hdr, status, s_scan);
 }
 
-template <int W>
+template <class Walk>
+__device__ __forceinline__ const typename Walk::Dev &dev_of(const BatchIndex &bi)
+{
+    if constexpr (std::is_same<typename Walk::Dev, AcDev>::value)
+        return bi.ac;
+    else
+        return bi.wm;
+}
+
+// One launch serves one walker kind (algorithm, table placement, byte-class
+// method); a batch's texts are split into launches by kind and block size.
+template <class Walk, int W>
 __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
 {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -1307,7 +1344,7 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
     const BatchText *const texts = bd.texts;
     if (threadIdx.x == 0)
         s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t loaded = 0xffffffffu;  // (index << 8) | kind held in LDS (uniform)
+    uint32_t loaded = 0xffffffffu;  // index whose tables LDS holds (uniform)
 
     while (true) {
         if (threadIdx.x == 0) {
@@ -1329,74 +1366,42 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
         const uint64_t g = s_tile;
         if (g >= ntiles)
             break;
-        const uint32_t kind = s_bt.kind;
         const uint32_t ix = s_bt.index;
-        const BatchIndex &bi = bd.idx[ix];
-        const uint32_t key = (ix << 8) | kind;
-        if (key != loaded) {
-            switch (kind & BK_WALK_MASK) {
-            case BK_AC16_LDS: AcWalk<uint16_t, true, false, 1>::load<W>(bi.ac); break;
-            case BK_AC16_GLB: AcWalk<uint16_t, false, false, 1>::load<W>(bi.ac); break;
-            case BK_AC32_GLB: AcWalk<uint32_t, false, false, 1>::load<W>(bi.ac); break;
-            case BK_WM_LDS: WmWalk<true>::load<W>(bi.wm); break;
-            default: break;
-            }
+        const auto &dev = dev_of<Walk>(bd.idx[ix]);
+        if (ix != loaded) {
+            Walk::template load<W>(dev);
             __syncthreads();
-            loaded = key;
+            loaded = ix;
         }
-        const uint32_t L = s_bt.lane_bytes;
-        glb_cptr<uint8_t> text = (glb_cptr<uint8_t>)s_bt.td.text;
-        const uint64_t n = s_bt.td.n;
-        mpm_match *const out = s_bt.td.out;
-        const uint64_t cap = s_bt.td.cap;
-        uint64_t *const total = s_bt.td.total;
-        const uint64_t first_g = s_bt.td.tile_begin;
-        const uint64_t nt = s_bt.td.ntiles;
-        const uint32_t epoch = s_epoch;
-        const bool swar = (kind & BK_SWAR) != 0;
-        switch (kind & BK_WALK_MASK) {
-        case BK_AC16_LDS:
-            if (swar)
-                batch_chunk<AcWalk<uint16_t, true, true, 1>, W>(bi.ac, text, n, out, cap, total,
-                                                                first_g, nt, g, L, epoch, hdr,
-                                                                status, s_scan);
-            else
-                batch_chunk<AcWalk<uint16_t, true, false, 1>, W>(bi.ac, text, n, out, cap,
-                                                                 total, first_g, nt, g, L, epoch,
-                                                                 hdr, status, s_scan);
-            break;
-        case BK_AC16_GLB:
-            if (swar)
-                batch_chunk<AcWalk<uint16_t, false, true, 1>, W>(bi.ac, text, n, out, cap,
-                                                                 total, first_g, nt, g, L, epoch,
-                                                                 hdr, status, s_scan);
-            else
-                batch_chunk<AcWalk<uint16_t, false, false, 1>, W>(bi.ac, text, n, out, cap,
-                                                                  total, first_g, nt, g, L, epoch,
-                                                                  hdr, status, s_scan);
-            break;
-        case BK_AC32_GLB:
-            if (swar)
-                batch_chunk<AcWalk<uint32_t, false, true, 1>, W>(bi.ac, text, n, out, cap,
-                                                                 total, first_g, nt, g, L, epoch,
-                                                                 hdr, status, s_scan);
-            else
-                batch_chunk<AcWalk<uint32_t, false, false, 1>, W>(bi.ac, text, n, out, cap,
-                                                                  total, first_g, nt, g, L, epoch,
-                                                                  hdr, status, s_scan);
-            break;
-        case BK_WM_LDS:
-            batch_chunk<WmWalk<true>, W>(bi.wm, text, n, out, cap, total, first_g, nt, g, L,
-                                         epoch, hdr, status, s_scan);
-            break;
-        default:
-            batch_chunk<WmWalk<false>, W>(bi.wm, text, n, out, cap, total, first_g, nt, g, L,
-                                          epoch, hdr, status, s_scan);
-            break;
-        }
+        batch_chunk<Walk, W>(dev, (glb_cptr<uint8_t>)s_bt.td.text, s_bt.td.n, s_bt.td.out,
+                             s_bt.td.cap, s_bt.td.total, s_bt.td.tile_begin, s_bt.td.ntiles, g,
+                             s_bt.lane_bytes, s_epoch, hdr, status, s_scan);
         __syncthreads();
     }
     finish_launch(hdr, s_epoch);
+}
+
+template <class Walk>
+static const void *batch_pick_w(uint32_t W)
+{
+    switch (W) {
+    case 256: return (const void *)batch_kernel<Walk, 256>;
+    case 512: return (const void *)batch_kernel<Walk, 512>;
+    case 1024: return (const void *)batch_kernel<Walk, 1024>;
+    }
+    return nullptr;
+}
+
+template <class Walk>
+static hipError_t batch_launch_w(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds,
+                                 hipStream_t s)
+{
+    switch (W) {
+    case 256: hipLaunchKernelGGL((batch_kernel<Walk, 256>), dim3(grid), dim3(256), lds, s, bd); break;
+    case 512: hipLaunchKernelGGL((batch_kernel<Walk, 512>), dim3(grid), dim3(512), lds, s, bd); break;
+    default: hipLaunchKernelGGL((batch_kernel<Walk, 1024>), dim3(grid), dim3(1024), lds, s, bd); break;
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1437,9 +1442,28 @@ static hipError_t launch_w(const typename Walk::Dev &a, const LaunchCfg &c, cons
 }
 
 // Kernel families, one translation unit each.
-const void *batch_kernel_ptr(uint32_t W);
-hipError_t batch_launch(const BatchDev &bd, uint32_t W, uint32_t grid, uint32_t lds,
-                        hipStream_t s);
+template <int P> const void *batch_kernel_ac16(bool swar, uint32_t W);
+template <int P>
+hipError_t batch_launch_ac16(const BatchDev &bd, bool swar, uint32_t W, uint32_t grid, uint32_t lds,
+                             hipStream_t s);
+// One translation unit per placement, each defining its specialisation.
+#define MPM_BATCH_AC16_TU(P)                                                                      \
+    template <>                                                                                   \
+    const void *batch_kernel_ac16<P>(bool swar, uint32_t W)                                       \
+    {                                                                                             \
+        return swar ? batch_pick_w<AcWalk<uint16_t, P, true, 1>>(W)                               \
+                    : batch_pick_w<AcWalk<uint16_t, P, false, 1>>(W);                             \
+    }                                                                                             \
+    template <>                                                                                   \
+    hipError_t batch_launch_ac16<P>(const BatchDev &bd, bool swar, uint32_t W, uint32_t grid,     \
+                                    uint32_t lds, hipStream_t s)                                  \
+    {                                                                                             \
+        return swar ? batch_launch_w<AcWalk<uint16_t, P, true, 1>>(bd, W, grid, lds, s)           \
+                    : batch_launch_w<AcWalk<uint16_t, P, false, 1>>(bd, W, grid, lds, s);         \
+    }
+const void *batch_kernel_other(uint32_t kind, uint32_t W);
+hipError_t batch_launch_other(const BatchDev &bd, uint32_t kind, uint32_t W, uint32_t grid,
+                              uint32_t lds, hipStream_t s);
 const void *wm_kernel(const LaunchCfg &c);
 hipError_t wm_launch(const WmDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 

@@ -25,18 +25,21 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (MPM_EUNSUPPORTED, MPM_OK, MpmError, PLACE_GLOBAL, PLACE_LDS, Index, Variant,
+from . import (MPM_EUNSUPPORTED, MPM_OK, MpmError, PLACE_AUTO, PLACE_GLOBAL, Index, Variant,
                _check, _L, _stream_handle, _torch, build_ac, build_wm)
 
 ALGOS = ("ac", "wm")
 LANE_BYTES = (64, 256, 1024)
 BLOCK_THREADS = (256, 512)
-PLACEMENTS = (PLACE_LDS, PLACE_GLOBAL)
+# Placement of the matching tables: in LDS as far as they go (all of them when
+# they fit, else the hot part: the shallow Aho-Corasick states or the
+# Wu-Manber SHIFT table), or all in global memory.
+PLACEMENTS = (PLACE_AUTO, PLACE_GLOBAL)
 
 # (algo, lane_bytes, block_threads, placement), 24 entries in a fixed order.
 VARIANTS = [(a, L, W, P) for a in ALGOS for L in LANE_BYTES for W in BLOCK_THREADS
             for P in PLACEMENTS]
-DEFAULT_VARIANT = VARIANTS.index(("ac", 1024, 512, PLACE_LDS))
+DEFAULT_VARIANT = VARIANTS.index(("ac", 1024, 512, PLACE_AUTO))
 
 FEATURES = ("log2_n", "log2_d", "m", "alphabet", "log2_states", "wm_mean_shift", "density")
 
@@ -64,7 +67,7 @@ class PatternSetIndexes:
 
     def lds_fits(self, k: int) -> bool:
         """Whether variant k can run (LDS placement needs the tables to fit)."""
-        if VARIANTS[k][3] != PLACE_LDS:
+        if VARIANTS[k][3] != PLACEMENTS[0]:
             return True
         from . import workspace_bytes
         try:

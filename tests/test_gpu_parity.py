@@ -181,3 +181,33 @@ def test_est256_full_list(mpm, algo):
     found = set(zip(got[0].tolist(), got[1].tolist()))
     for r, s in enumerate(ps.planted_starts.tolist()):
         assert (s, r) in found
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_hot_placement_large_tables(mpm, algo):
+    """Tables larger than LDS: the hot part in LDS (the first rows of the
+    Aho-Corasick table in breadth-first order; the Wu-Manber SHIFT table), the
+    rest read through the caches. Bit-exact against the oracle, alone and as
+    the automatic choice, at text offsets 0 and 5."""
+    t = synth.est_text(2_500_000, seed=31)
+    if algo == "ac":
+        ps = synth.pattern_set(t, d=3000, m=20, n_planted=1500, seed=32)
+    else:
+        ps = synth.pattern_set(t, d=20000, m=16, n_planted=2000, seed=33)
+    want = oracle.Win(ps.patterns).scan(t)
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(ps.patterns, upload=True)
+    info = ix.info()
+    assert info["table_bytes"] > 160 * 1024
+    if algo == "ac":
+        assert info["state_bytes"] == 2
+    with pytest.raises(mpm.MpmError):  # the whole table does not fit
+        mpm.workspace_bytes(ix, len(t), mpm.variant(lane_bytes=64, block_threads=256,
+                                                    placement=mpm.PLACE_LDS))
+    for mis in (0, 5):
+        for v in (dict(lane_bytes=64, block_threads=256, placement=mpm.PLACE_HOT),
+                  dict(lane_bytes=1024, block_threads=1024, placement=mpm.PLACE_HOT),
+                  dict(lane_bytes=256, block_threads=512, placement=mpm.PLACE_AUTO),
+                  dict(lane_bytes=128, block_threads=256, placement=mpm.PLACE_HOT, flags=1)):
+            say(f"[hot] {algo} d={len(ps.patterns)} misalign={mis} {v}")
+            got = gpu_pairs(mpm, ix, t, mpm.variant(**v), misalign=mis)
+            assert_same(got, want, f"hot {algo} mis={mis} {v}")
