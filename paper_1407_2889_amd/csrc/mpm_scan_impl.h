@@ -22,14 +22,18 @@
 // Walkers:
 //   AC - one dependent lookup per byte in the dense table (Section 3.1, array
 //        form of the goto function with supply transitions precomputed); the
-//        table sits in LDS when it fits, otherwise it is read through L2.
-//        Text bytes are read by each lane with 16-byte loads, one 64-byte
-//        block ahead of use.
-//   WM - the chunk's text is staged in LDS with 16-byte coalesced loads
-//        (Section 4.2.2, collective reads into shared memory); each lane then
-//        runs the Wu-Manber window loop (Section 3.2, Algorithm 5) over its
-//        window ends with SHIFT in LDS or L2, and verifies candidate windows
-//        against HASH/PREFIX and the pattern bytes.
+//        table sits in LDS when it fits, else its first (shallow) rows do and
+//        the rest is read through the caches, else all of it is read through
+//        the caches. Each lane streams its text as whole 128-byte lines of
+//        16-byte loads, the next line in flight while the current one is
+//        walked (the paper stages text in shared memory, Section 4.2.2; on
+//        this hardware a lane's own whole-line loads move full cache lines and
+//        LDS is left to the table).
+//   WM - each lane runs the Wu-Manber window loop (Section 3.2, Algorithm 5)
+//        over its window ends on a history of 2-bit character codes held in
+//        registers, with SHIFT in LDS (or read through the caches), and
+//        verifies candidate windows against the bucket (HASH), a filter key
+//        (PREFIX) and the pattern bytes.
 #pragma once
 #include <hip/hip_runtime.h>
 
