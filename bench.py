@@ -146,7 +146,8 @@ def run_sweep(args):
     {8, 16, 32}, 10% planted; every (set, algorithm) scanned with the full
     sorted list written. One JSON line with one record per (set, algorithm):
     text GB/s, the HBM roofline fraction of the algorithmic bytes, the match
-    count and a digest of the per-pattern counts."""
+    count, and a digest of the per-pattern counts (counted on the device from
+    the list, timed separately as count_ms)."""
     import torch
     import paper_1407_2889_amd as mpm
     import synth
@@ -175,7 +176,18 @@ def run_sweep(args):
                 kms = time_scans(sc, dev, args.steps, args.warmup, stream)
                 t_all += kms * args.steps
                 lists[algo] = sc.out[:M]
-                counts = torch.bincount(sc.out[:M, 1].to(torch.int64), minlength=d)
+                cbuf = torch.empty(d, dtype=torch.int32, device=dev.device)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                mpm.count_ids(sc.out[:M], d, out=cbuf)
+                ev[0].record(stream)
+                for _ in range(args.steps):
+                    mpm.count_ids(sc.out[:M], d, out=cbuf)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                count_ms = ev[0].elapsed_time(ev[1]) / args.steps
+                counts = cbuf.to(torch.int64) & 0xFFFFFFFF
+                if int(counts.sum()) != M:
+                    raise SystemExit(f"per-pattern counts do not sum to the list length at d={d} m={m}")
                 alg_bytes = n + 8 * M + info["table_bytes"]
                 rows.append({
                     "d": d, "m": m, "algo": algo, "gbps": round(n / (kms * 1e-3) / 1e9, 2),
@@ -184,8 +196,9 @@ def run_sweep(args):
                     "table_bytes": info["table_bytes"],
                     "states": info["n_states"] if algo == "ac" else None,
                     "wm_block": info["wm_block"] if algo == "wm" else None,
-                    "placement": "lds" if info["table_bytes"] + 1024 <= 160 * 1024 else "global",
+                    "placement": "lds" if info["table_bytes"] + 1024 <= 160 * 1024 else "hot",
                     "patterns_hit": int((counts > 0).sum()), "max_count": int(counts.max()),
+                    "count_ms": round(count_ms, 4),
                     "build_s": round(build_s, 3)})
                 log(f"[bench] d={d} m={m} {algo}: {rows[-1]['gbps']} GB/s, {M} matches")
                 del sc, count, ix
@@ -269,7 +282,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the scan shards by contiguous text ranges across GPUs, but this build "
+              "the scan shards by contiguous text ranges across GPUs, but this benchmark "
               "measures one GPU", file=sys.stderr)
         sys.exit(2)
     if args.workload == "sweep":

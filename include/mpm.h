@@ -77,11 +77,10 @@ typedef struct {
 #define MPM_PLACE_LDS 1     /* matching tables copied into LDS once per workgroup */
 #define MPM_PLACE_GLOBAL 2  /* matching tables read through the L2/L1 caches */
 #define MPM_PLACE_HOT 3     /* the part of the tables read on nearly every step in LDS, the
-                               rest through the caches: Aho-Corasick tables with 16-bit
-                               entries keep their first rows in breadth-first order (the
-                               shallow states a walk over text visits), Wu-Manber keeps
-                               SHIFT and leaves the buckets global. Other indexes:
-                               EUNSUPPORTED */
+                               rest through the caches: Aho-Corasick keeps its first rows
+                               in breadth-first order (the shallow states a walk over text
+                               visits), Wu-Manber keeps SHIFT and leaves the buckets
+                               global. EUNSUPPORTED with MPM_VARIANT_ILP2 */
 
 /* Launch variant of a scan. Zero fields take defaults. The text is split
  * into chunks of lane_bytes * block_threads starting positions; each lane owns
@@ -198,6 +197,18 @@ mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n
                          mpm_match *d_out, uint64_t capacity, void *d_work, uint64_t work_bytes,
                          uint64_t *d_total, const mpm_variant *v, void *stream,
                          uint64_t *total);
+
+/* Per-pattern occurrence counts of a match list: d_counts[r] = number of
+ * pairs in d_pairs whose id is r (Section 4.2: the per-thread counts, each
+ * terminal adding the number of patterns it stands for, summed per pattern;
+ * their sum is the list's length). One pass over the list, enqueued on
+ * `stream`, no wait.
+ *   d_pairs:  device, M pairs as written by mpm_scan (8-byte aligned); may be
+ *             NULL iff M == 0. Pairs whose id is not below d are not counted.
+ *   d_counts: device uint32[d], caller-owned; overwritten (zeroed first).
+ * Errors: EINVAL (d == 0, null or unaligned pointers), EHIP. */
+mpm_status mpm_count_ids(const mpm_match *d_pairs, uint64_t M, uint32_t d, uint32_t *d_counts,
+                         void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Scanning many texts in one replayable launch                            */

@@ -124,6 +124,7 @@ _sig("mpm_export_ac", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_export_wm_shift", C.c_int32, [_vp, _vp])
 _sig("mpm_export_unique", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_read_probe", C.c_int32, [_vp, _u64, _vp, _vp])
+_sig("mpm_count_ids", C.c_int32, [_vp, _u64, _u32, _vp, _vp])
 _sig("mpm_tune_time", C.c_int32, [_vp, _vp, _u64, _u32, C.POINTER(Variant), _vp, _u64, _vp, _vp,
                                   _u64, _u32, _vp, C.POINTER(C.c_float)])
 _sig("mpm_tune_work_bytes", _u64, [_vp, _u64, _u32, C.POINTER(Variant)])
@@ -142,7 +143,7 @@ EXPORTS = [
     "mpm_batch_replay", "mpm_batch_groups", "mpm_batch_free", "mpm_export_ac",
     "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
     "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
-    "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam",
+    "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam", "mpm_count_ids",
 ]
 
 
@@ -349,6 +350,20 @@ def scan(ix: Index, text, capacity: int | None = None, var: Variant | None = Non
         _check(st, "mpm_scan_sync")
         return out[: tot.value]
     raise MpmError(MPM_EOVERFLOW, "scan")
+
+
+def count_ids(pairs, d: int, out=None, stream=None):
+    """Per-pattern counts of an int32 [M, 2] (pos, id) device list: int32 [d]
+    tensor (values are uint32 counts) with out[r] = number of pairs of id r."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(d, dtype=torch.int32, device=pairs.device)
+    assert out.numel() >= d and out.dtype == torch.int32 and out.is_contiguous()
+    assert pairs.dtype == torch.int32 and pairs.is_contiguous() and (pairs.numel() == 0 or pairs.shape[1] == 2)
+    M = pairs.shape[0] if pairs.numel() else 0
+    _check(_L.mpm_count_ids(C.c_void_p(pairs.data_ptr() if M else 0), M, d,
+                            C.c_void_p(out.data_ptr()), _stream_handle(stream)), "mpm_count_ids")
+    return out[:d]
 
 
 def read_probe(buf, sink, stream=None):

@@ -114,6 +114,7 @@ enum {
     BK_WM_GLB = 4,
     BK_AC16_HOT = 5,
     BK_WM_HOT = 6,
+    BK_AC32_HOT = 7,
     BK_WALK_MASK = 0x7f,
     BK_SWAR = 0x80
 };

@@ -16,6 +16,8 @@ const void *ac16_glb_kernel(const LaunchCfg &c);
 const void *ac16_hot_kernel(const LaunchCfg &c);
 hipError_t ac16_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 const void *ac32_glb_kernel(const LaunchCfg &c);
+const void *ac32_hot_kernel(const LaunchCfg &c);
+hipError_t ac32_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 hipError_t ac16_lds_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 hipError_t ac16_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 hipError_t ac32_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
@@ -135,7 +137,7 @@ WmDev wm_dev(const mpm_index *ix)
 // Whether an index can run with the hot part of its tables in LDS.
 static bool has_hot(const mpm_index *ix)
 {
-    return ix->algo == MPM_ALGO_WM || (ix->algo == MPM_ALGO_AC && ix->state_bytes == 2);
+    return ix->algo == MPM_ALGO_WM || ix->algo == MPM_ALGO_AC;
 }
 
 // LDS bytes of the hot part.
@@ -149,8 +151,8 @@ static uint64_t hot_lds_bytes(const mpm_index *ix)
 static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
 {
     if (ix->algo == MPM_ALGO_AC) {
-        if (ix->state_bytes == 4)
-            return ac32_glb_kernel(c);  // tables of 2^16 states or more never fit in LDS
+        if (ix->state_bytes == 4)  // tables of 2^16 states or more never fit whole in LDS
+            return c.placement == MPM_PLACE_HOT ? ac32_hot_kernel(c) : ac32_glb_kernel(c);
         if (c.placement == MPM_PLACE_HOT)
             return ac16_hot_kernel(c);
         return c.placement == MPM_PLACE_LDS ? ac16_lds_kernel(c) : ac16_glb_kernel(c);
@@ -249,7 +251,7 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
     if (ix->algo == MPM_ALGO_AC) {
         const AcDev a = ac_dev(ix);
         if (ix->state_bytes == 4)
-            e = ac32_glb_launch(a, c, sd, s);
+            e = c.placement == MPM_PLACE_HOT ? ac32_hot_launch(a, c, sd, s) : ac32_glb_launch(a, c, sd, s);
         else if (c.placement == MPM_PLACE_HOT)
             e = ac16_hot_launch(a, c, sd, s);
         else
@@ -266,7 +268,7 @@ uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c)
 {
     uint32_t k;
     if (ix->algo == MPM_ALGO_AC)
-        k = ix->state_bytes == 4               ? BK_AC32_GLB
+        k = ix->state_bytes == 4 ? (c.placement == MPM_PLACE_HOT ? BK_AC32_HOT : BK_AC32_GLB)
             : c.placement == MPM_PLACE_LDS     ? BK_AC16_LDS
             : c.placement == MPM_PLACE_HOT     ? BK_AC16_HOT
                                                : BK_AC16_GLB;

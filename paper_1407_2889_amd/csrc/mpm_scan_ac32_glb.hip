@@ -1,4 +1,5 @@
-// Aho-Corasick scan kernels: uint32_t table entries, table in global memory.
+// Aho-Corasick scan kernels: uint32_t table entries, table in global memory
+// or its first rows in LDS (hot placement, one chain per lane).
 #include "mpm_scan_impl.h"
 
 namespace mpm {
@@ -10,6 +11,18 @@ const void *ac32_glb_kernel(const LaunchCfg &c)
                     : pick_w<AcWalk<uint32_t, false, true, 1>>(c.block_threads))
               : (i2 ? pick_w<AcWalk<uint32_t, false, false, 2>>(c.block_threads)
                     : pick_w<AcWalk<uint32_t, false, false, 1>>(c.block_threads));
+}
+
+const void *ac32_hot_kernel(const LaunchCfg &c)
+{
+    return c.swar ? pick_w<AcWalk<uint32_t, PL_HOT, true, 1>>(c.block_threads)
+                  : pick_w<AcWalk<uint32_t, PL_HOT, false, 1>>(c.block_threads);
+}
+
+hipError_t ac32_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s)
+{
+    return c.swar ? launch_w<AcWalk<uint32_t, PL_HOT, true, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
+                  : launch_w<AcWalk<uint32_t, PL_HOT, false, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s);
 }
 
 hipError_t ac32_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s)

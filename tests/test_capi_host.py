@@ -169,3 +169,26 @@ def test_wm_auto_block_prefers_long_blocks_for_sparse_sets():
     inf = mpm.build_wm(P).info()
     assert inf["wm_block"] >= 6
     assert inf["wm_mean_shift"] > 5
+
+
+def test_placement_resolution():
+    """Tables larger than LDS: whole-LDS placement is refused, the hot part in
+    LDS (or all of it global) is accepted, automatic placement picks one of
+    them, and the two-chain variant has no hot placement. Host-only."""
+    rng = np.random.default_rng(21)
+    P = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, (3000, 20))]
+    for build in (mpm.build_ac, mpm.build_wm):
+        ix = build(P)
+        assert ix.info()["table_bytes"] > 160 * 1024
+        with pytest.raises(mpm.MpmError) as e:
+            mpm.workspace_bytes(ix, 1 << 20, mpm.variant(64, 256, mpm.PLACE_LDS))
+        assert e.value.status == mpm.MPM_EUNSUPPORTED
+        for pl in (mpm.PLACE_AUTO, mpm.PLACE_GLOBAL, mpm.PLACE_HOT):
+            assert mpm.workspace_bytes(ix, 1 << 20, mpm.variant(64, 256, pl)) > 0
+    ix = mpm.build_ac(P)
+    with pytest.raises(mpm.MpmError) as e:
+        mpm.workspace_bytes(ix, 1 << 20, mpm.variant(64, 256, mpm.PLACE_HOT, 0, mpm.VARIANT_ILP2))
+    assert e.value.status == mpm.MPM_EUNSUPPORTED
+    with pytest.raises(mpm.MpmError) as e:
+        mpm.workspace_bytes(ix, 1 << 20, mpm.variant(64, 256, 4))
+    assert e.value.status == mpm.MPM_EINVAL

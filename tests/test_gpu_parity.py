@@ -183,7 +183,7 @@ def test_est256_full_list(mpm, algo):
         assert (s, r) in found
 
 
-@pytest.mark.parametrize("algo", ["ac", "wm"])
+@pytest.mark.parametrize("algo", ["ac", "ac32", "wm"])
 def test_hot_placement_large_tables(mpm, algo):
     """Tables larger than LDS: the hot part in LDS (the first rows of the
     Aho-Corasick table in breadth-first order; the Wu-Manber SHIFT table), the
@@ -192,14 +192,16 @@ def test_hot_placement_large_tables(mpm, algo):
     t = synth.est_text(2_500_000, seed=31)
     if algo == "ac":
         ps = synth.pattern_set(t, d=3000, m=20, n_planted=1500, seed=32)
+    elif algo == "ac32":
+        ps = synth.pattern_set(t, d=6000, m=20, n_planted=3000, seed=34)
     else:
         ps = synth.pattern_set(t, d=20000, m=16, n_planted=2000, seed=33)
     want = oracle.Win(ps.patterns).scan(t)
-    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(ps.patterns, upload=True)
+    ix = (mpm.build_wm if algo == "wm" else mpm.build_ac)(ps.patterns, upload=True)
     info = ix.info()
     assert info["table_bytes"] > 160 * 1024
-    if algo == "ac":
-        assert info["state_bytes"] == 2
+    if algo != "wm":
+        assert info["state_bytes"] == (2 if algo == "ac" else 4)
     with pytest.raises(mpm.MpmError):  # the whole table does not fit
         mpm.workspace_bytes(ix, len(t), mpm.variant(lane_bytes=64, block_threads=256,
                                                     placement=mpm.PLACE_LDS))
@@ -211,3 +213,39 @@ def test_hot_placement_large_tables(mpm, algo):
             say(f"[hot] {algo} d={len(ps.patterns)} misalign={mis} {v}")
             got = gpu_pairs(mpm, ix, t, mpm.variant(**v), misalign=mis)
             assert_same(got, want, f"hot {algo} mis={mis} {v}")
+
+
+def test_per_pattern_counts(mpm, small):
+    """Per-pattern counts of the scan's list (the counts of Section 4.2 summed
+    per pattern) against the oracle's list counted per id, on the 1 MiB
+    workload and on a dense set whose id range spans two LDS histograms."""
+    text, P, want = small
+    ix = mpm.build_ac(P, upload=True)
+    out = mpm.scan(ix, to_dev(text))
+    got = mpm.count_ids(out, len(P)).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, np.bincount(want[1], minlength=len(P)))
+    t = synth.est_text(1_500_000, seed=41)
+    ps = synth.pattern_set(t, d=50000, m=8, n_planted=5000, seed=42)
+    want = oracle.Win(ps.patterns).scan(t)
+    ix = mpm.build_wm(ps.patterns, upload=True)
+    out = mpm.scan(ix, to_dev(t))
+    assert out.shape[0] == len(want[0]) > 100_000
+    got = mpm.count_ids(out, 50000).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, np.bincount(want[1], minlength=50000))
+
+
+def test_per_pattern_counts_edges(mpm):
+    """Counting edge cases on synthetic lists: an empty list zeroes the
+    counts, ids not below d are skipped, a list length that is not a multiple
+    of the unrolled stride, and three id slices."""
+    c = torch.full((100,), 7, dtype=torch.int32, device="cuda")
+    mpm.count_ids(torch.empty((0, 2), dtype=torch.int32, device="cuda"), 100, out=c)
+    assert int(c.abs().sum()) == 0
+    rng = np.random.default_rng(43)
+    for d, M in ((1, 5), (100, 1), (1000, 3_000_001), (100_000, 2_000_003)):
+        ids = rng.integers(0, d + 50, M).astype(np.uint32)
+        pairs = np.stack([np.arange(M, dtype=np.uint32), ids], axis=1)
+        dev = torch.from_numpy(pairs.view(np.int32)).cuda()
+        say(f"[counts] d={d} M={M}")
+        got = mpm.count_ids(dev, d).cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, np.bincount(ids[ids < d], minlength=d)), (d, M)
