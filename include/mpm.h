@@ -198,6 +198,30 @@ mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n
                          uint64_t *d_total, const mpm_variant *v, void *stream,
                          uint64_t *total);
 
+/* Scan a text that stays in host memory (Section 5: the texts exceeded device
+ * memory and the kernels read them from host memory). The text is cut into
+ * chunks of `chunk` starting positions; each chunk and the m - 1 bytes after
+ * it are copied into one half of d_stage on a copy stream the call creates
+ * (default priority) while the previous chunk is scanned on `stream`. Waits
+ * for completion; the result is that of mpm_scan_sync on the whole text.
+ *   h_text:      host, n bytes. Pinned memory (hipHostMalloc) lets the copies
+ *                overlap the scans; pageable memory works, serialized.
+ *   d_stage:     device staging buffer of stage_bytes >= 2 * (c + m - 1)
+ *                bytes, c = min(chunk, n - m + 1) (one half suffices when the
+ *                text is a single chunk).
+ *   chunk:       starting positions per chunk, >= 1.
+ *   d_out, capacity, v: as mpm_scan; positions are offsets into h_text.
+ *   d_work:      workspace of mpm_workspace_bytes(idx, c + m - 1, v) bytes.
+ *   d_total:     device uint64 scratch.
+ *   total:       host; receives the full number of pairs.
+ * Errors: EINVAL, ETOOBIG, ENOMEM (staging or workspace too small), EHIP,
+ * ESTATE, and EOVERFLOW as mpm_scan_sync (the first `capacity` pairs valid). */
+mpm_status mpm_scan_host(const mpm_index *idx, const uint8_t *h_text, uint64_t n,
+                         uint8_t *d_stage, uint64_t stage_bytes, uint64_t chunk,
+                         mpm_match *d_out, uint64_t capacity, void *d_work, uint64_t work_bytes,
+                         uint64_t *d_total, const mpm_variant *v, void *stream,
+                         uint64_t *total);
+
 /* Per-pattern occurrence counts of a match list: d_counts[r] = number of
  * pairs in d_pairs whose id is r (Section 4.2: the per-thread counts, each
  * terminal adding the number of patterns it stands for, summed per pattern;

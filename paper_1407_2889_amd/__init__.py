@@ -125,6 +125,8 @@ _sig("mpm_export_wm_shift", C.c_int32, [_vp, _vp])
 _sig("mpm_export_unique", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_read_probe", C.c_int32, [_vp, _u64, _vp, _vp])
 _sig("mpm_count_ids", C.c_int32, [_vp, _u64, _u32, _vp, _vp])
+_sig("mpm_scan_host", C.c_int32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _u64, _vp, _u64, _vp,
+                                  C.POINTER(Variant), _vp, C.POINTER(_u64)])
 _sig("mpm_tune_time", C.c_int32, [_vp, _vp, _u64, _u32, C.POINTER(Variant), _vp, _u64, _vp, _vp,
                                   _u64, _u32, _vp, C.POINTER(C.c_float)])
 _sig("mpm_tune_work_bytes", _u64, [_vp, _u64, _u32, C.POINTER(Variant)])
@@ -144,6 +146,7 @@ EXPORTS = [
     "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
     "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
     "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam", "mpm_count_ids",
+    "mpm_scan_host",
 ]
 
 
@@ -350,6 +353,46 @@ def scan(ix: Index, text, capacity: int | None = None, var: Variant | None = Non
         _check(st, "mpm_scan_sync")
         return out[: tot.value]
     raise MpmError(MPM_EOVERFLOW, "scan")
+
+
+def scan_host(ix: Index, text, chunk: int = 64 << 20, capacity: int | None = None,
+              var: Variant | None = None, stream=None):
+    """Scan a text held in host memory (a uint8 CPU tensor, pinned for
+    overlap, or a numpy array, copied into pinned memory first), `chunk`
+    starting positions per device copy. Returns int32 [M, 2] (pos, id) on
+    the current device; grows the output once if the first capacity was
+    short."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if isinstance(text, np.ndarray):
+        t = torch.empty(len(text), dtype=torch.uint8, pin_memory=True)
+        t.numpy()[:] = text
+        text = t
+    assert text.dtype == torch.uint8 and text.device.type == "cpu" and text.is_contiguous()
+    if not ix.uploaded:
+        ix.upload(dev)
+    n = text.numel()
+    ns = max(0, n - ix.m + 1)
+    c = max(1, min(chunk, ns))
+    nch = (ns + c - 1) // c if ns else 1
+    stage = torch.empty((2 if nch > 1 else 1) * (c + ix.m - 1), dtype=torch.uint8, device=dev)
+    ws = new_workspace(ix, c + ix.m - 1, var, dev)
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+    cap = capacity if capacity is not None else n // 32 + 4096
+    for _ in range(2):
+        out = torch.empty((max(1, cap), 2), dtype=torch.int32, device=dev)
+        tot = C.c_uint64()
+        st = _L.mpm_scan_host(ix.handle, C.c_void_p(text.data_ptr() if n else 0), n,
+                              C.c_void_p(stage.data_ptr()), stage.numel(), c,
+                              C.c_void_p(out.data_ptr()), cap, C.c_void_p(ws.data_ptr()),
+                              ws.numel() * 8, C.c_void_p(total.data_ptr()),
+                              C.byref(var) if var else None, _stream_handle(stream), C.byref(tot))
+        if st == MPM_EOVERFLOW and capacity is None:
+            cap = int(tot.value)
+            continue
+        _check(st, "mpm_scan_host")
+        return out[: tot.value]
+    raise MpmError(MPM_EOVERFLOW, "scan_host")
 
 
 def count_ids(pairs, d: int, out=None, stream=None):

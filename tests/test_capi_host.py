@@ -53,6 +53,17 @@ def test_error_codes():
     st = mpm._L.mpm_scan_sync(ix.handle, C.c_void_p(16), 8, None, 0, C.c_void_p(64), 1 << 20,
                               C.c_void_p(8), None, None, C.byref(tot))
     assert st == mpm.MPM_ESTATE
+    # host-streamed scan and per-pattern counts: argument checks, no device work
+    def scan_host(n, chunk):
+        return mpm._L.mpm_scan_host(ix.handle, C.c_void_p(16), n, C.c_void_p(64), 1 << 20, chunk,
+                                    None, 0, C.c_void_p(64), 1 << 20, C.c_void_p(8), None, None,
+                                    C.byref(tot))
+    assert scan_host(100, 0) == mpm.MPM_EINVAL
+    assert scan_host(1 << 32, 1024) == mpm.MPM_ETOOBIG
+    assert scan_host(3, 1024) == mpm.MPM_ESTATE  # n < m: a scan of nothing, index not uploaded
+    assert mpm._L.mpm_count_ids(None, 0, 0, C.c_void_p(64), None) == mpm.MPM_EINVAL
+    assert mpm._L.mpm_count_ids(C.c_void_p(4), 1, 10, C.c_void_p(64), None) == mpm.MPM_EINVAL
+    assert mpm._L.mpm_count_ids(None, 5, 10, C.c_void_p(64), None) == mpm.MPM_EINVAL
     with pytest.raises(mpm.MpmError):
         mpm.workspace_bytes(ix, 100, mpm.variant(lane_bytes=24))
     with pytest.raises(mpm.MpmError):
