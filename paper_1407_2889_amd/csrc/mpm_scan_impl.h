@@ -1023,19 +1023,23 @@ struct WmWalk {
             qp[k] = 0;
             qu[k] = 0;
         }
+        // Exact check of the queued candidates, eight bytes of window and
+        // pattern per step with no early exit, so a step's loads are in
+        // flight together.
         auto flush = [&]() {
 #pragma unroll
             for (int k = 0; k < WM_QUEUE; ++k) {
                 if ((uint32_t)k < qn) {
                     const uint64_t st = (uint64_t)qp[k] + 1 - m;
                     glb_cptr<uint8_t> pp = pats + (uint64_t)qu[k] * m;
-                    bool ok = true;
-                    for (uint32_t j = 0; j < m; ++j)
-                        if (pp[j] != text[st + j]) {
-                            ok = false;
-                            break;
-                        }
-                    if (ok)
+                    uint32_t diff = 0;
+                    for (uint32_t j = 0; j < m; j += 8) {
+#pragma unroll
+                        for (uint32_t t = 0; t < 8; ++t)
+                            if (j + t < m)
+                                diff |= (uint32_t)(pp[j + t] ^ text[st + j + t]);
+                    }
+                    if (diff == 0)
                         cb(st, qu[k]);
                 }
             }
@@ -1184,13 +1188,15 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
         if (nu[v] == 0)
             continue;
         uint64_t o = ob[v];
-        if (nu[v] <= (uint32_t)KS) {
 #pragma unroll
-            for (int k = 0; k < KS; ++k)
-                if ((uint32_t)k < nu[v])
-                    write_ids(out, cap, o, so[v][k], su[v][k], im);
-        } else {
-            wk.lane_again(text, n, base, lo[v], hi[v], [&](uint64_t start, uint32_t u) {
+        for (int k = 0; k < KS; ++k)
+            if ((uint32_t)k < nu[v])
+                write_ids(out, cap, o, so[v][k], su[v][k], im);
+        if (nu[v] > (uint32_t)KS) {
+            // The rest start after the last kept one (one distinct string per
+            // start): walk again from there, from the root / an empty window.
+            const uint32_t lo2 = (uint32_t)((uint64_t)so[v][KS - 1] + 1 - base);
+            wk.lane_again(text, n, base, lo2, hi[v], [&](uint64_t start, uint32_t u) {
                 write_ids(out, cap, o, (uint32_t)start, u, im);
             });
         }
