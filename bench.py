@@ -263,6 +263,48 @@ def run_stream(args):
     print(json.dumps(line), flush=True)
 
 
+def run_ablation(args):
+    """What the flattened table and its placement buy on the 256 MiB EST
+    text (d=1000, m=16): the goto function with supply links followed at run
+    time (the paper's kernel design, Section 4.2) against the flattened
+    table, each with the tables in global memory and, for the flattened
+    table, in LDS with and without register byte classes. Kernel time from
+    HIP events, the same lane ranges and workgroup size for every row; every
+    row's list is checked against the first. One JSON line."""
+    import torch
+    import paper_1407_2889_amd as mpm
+    text, ps, desc = workload("est256")
+    n = len(text)
+    dev = torch.from_numpy(text).cuda()
+    stream = torch.cuda.current_stream()
+    ix = mpm.build_ac(ps.patterns, upload=True, goto=True)
+    L, W = DEFAULT_VARIANTS["ac"]["lane_bytes"], DEFAULT_VARIANTS["ac"]["block_threads"]
+    rows_spec = [("flattened, LDS, register byte classes", mpm.PLACE_LDS, 0),
+                 ("flattened, LDS, byte-class table", mpm.PLACE_LDS, mpm.VARIANT_NO_SWAR),
+                 ("flattened, hot rows in LDS", mpm.PLACE_HOT, 0),
+                 ("flattened, global", mpm.PLACE_GLOBAL, 0),
+                 ("goto + supply links, global", mpm.PLACE_GLOBAL, mpm.VARIANT_SUPPLY)]
+    rows, ref = [], None
+    for name, pl, fl in rows_spec:
+        v = mpm.variant(lane_bytes=L, block_threads=W, placement=pl, flags=fl)
+        sc = mpm.Scanner(ix, n, capacity=1 << 20, var=v)
+        got = sc.scan(dev)
+        if ref is None:
+            ref = got.clone()
+        elif not torch.equal(got, ref):
+            raise SystemExit(f"ablation row '{name}' reports a different list")
+        kms = time_scans(sc, dev, args.steps, args.warmup, stream)
+        rows.append({"kernel": name, "kernel_ms": round(kms, 4), "gbps": round(n / (kms * 1e-3) / 1e9, 2)})
+        log(f"[bench] ablation {name}: {rows[-1]['gbps']} GB/s")
+        del sc
+    line = {"metric": "text GB/s scanned (AC kernel designs)", "workload": "ablation",
+            "config": {"workload": desc, "n_bytes": n, "lane_bytes": L, "block_threads": W,
+                       "matches": int(ref.shape[0]), "states": ix.info()["n_states"]},
+            "steps": args.steps, "warmup": args.warmup, "dtype": "u8", "data": "synthetic",
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def run_batched(args):
     """Batched workload with variant selection: a timing database of seeded
     training requests, the selector trained on it, then the 4,096-text batch
@@ -339,6 +381,8 @@ def main():
         return run_batched(args)
     if args.workload == "stream":
         return run_stream(args)
+    if args.workload == "ablation":
+        return run_ablation(args)
 
     import torch
     import paper_1407_2889_amd as mpm

@@ -69,7 +69,11 @@ typedef struct {
      * uniformly random text over the patterns' alphabet. Must satisfy
      * 1 <= B <= min(m, 8). Ignored by mpm_build_ac. */
     uint32_t wm_block;
-    uint32_t reserved[7];
+    /* Aho-Corasick: nonzero also keeps the goto function and the supply
+     * links (Algorithms 1-2) in the device image, for scans with
+     * MPM_VARIANT_SUPPLY. Ignored by mpm_build_wm. */
+    uint32_t ac_goto;
+    uint32_t reserved[6];
 } mpm_opts;
 
 #define MPM_PLACE_AUTO 0    /* LDS when the tables fit beside the scan's own LDS use, else
@@ -102,6 +106,13 @@ typedef struct {
  * (two independent table-lookup chains); a chunk then holds
  * 2 * lane_bytes * block_threads starting positions. */
 #define MPM_VARIANT_ILP2 2u
+/* Aho-Corasick: walk the goto function and follow supply links after a
+ * failed transition (the search of Algorithm 3 as the paper's kernels run
+ * it, Section 4.2) instead of the flattened table: the same result, kept to
+ * measure what the flattening buys. Needs an index built with ac_goto set;
+ * one chain per lane; placement LDS (when goto rows and supply links fit) or
+ * GLOBAL; single-text scans only (a batch plan refuses it). */
+#define MPM_VARIANT_SUPPLY 4u
 
 /* Facts about a built index. */
 typedef struct {

@@ -52,11 +52,12 @@ class MpmError(RuntimeError):
 
 
 class Opts(C.Structure):
-    _fields_ = [("wm_block", C.c_uint32), ("reserved", C.c_uint32 * 7)]
+    _fields_ = [("wm_block", C.c_uint32), ("ac_goto", C.c_uint32), ("reserved", C.c_uint32 * 6)]
 
 
 VARIANT_NO_SWAR = 1
 VARIANT_ILP2 = 2
+VARIANT_SUPPLY = 4
 
 
 class Variant(C.Structure):
@@ -251,12 +252,15 @@ class Index:
             pass
 
 
-def build_ac(patterns, upload: bool = False) -> Index:
-    """Aho-Corasick index (dense DFA). Host-only unless upload=True."""
+def build_ac(patterns, upload: bool = False, goto: bool = False) -> Index:
+    """Aho-Corasick index (dense DFA). Host-only unless upload=True. goto=True
+    also keeps the goto function and supply links for VARIANT_SUPPLY scans."""
     P = _patterns_np(patterns)
     h = C.c_void_p()
     Pp = P if P.size else np.zeros(1, np.uint8)
-    _check(_L.mpm_build_ac(Pp.ctypes.data, P.shape[0], P.shape[1], None, C.byref(h)),
+    o = Opts()
+    o.ac_goto = 1 if goto else 0
+    _check(_L.mpm_build_ac(Pp.ctypes.data, P.shape[0], P.shape[1], C.byref(o), C.byref(h)),
            "mpm_build_ac")
     ix = Index(h.value, ALGO_AC)
     return ix.upload() if upload else ix

@@ -18,7 +18,8 @@ SOURCES = ["mpm_host.cpp", "mpm_scan.hip", "mpm_scan_ac16_lds.hip", "mpm_scan_ac
            "mpm_scan_ac16_hot.hip", "mpm_scan_ac32_glb.hip", "mpm_scan_wm.hip",
            "mpm_scan_batch_ac16_lds.hip", "mpm_scan_batch_ac16_glb.hip",
            "mpm_scan_batch_ac16_hot.hip", "mpm_scan_batch_other.hip", "mpm_mlp.hip",
-           "mpm_count.hip", "mpm_stream.hip"]
+           "mpm_count.hip", "mpm_stream.hip",
+           "mpm_scan_ac_supply.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

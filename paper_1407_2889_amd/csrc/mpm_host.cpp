@@ -300,6 +300,32 @@ static mpm_status build_ac_tables(mpm_index *ix)
     }
     ix->off_c = put(ix->image, ix->uoff.data(), ix->uoff.size());
     ix->off_d = put(ix->image, ix->uids.data(), ix->uids.size());
+    if (ix->keep_goto) {
+        // Goto rows in the table's numbering and columns: a missing
+        // transition is all ones, except at the root, where it stays at the
+        // root (column 0, bytes of no pattern, included); then the supply
+        // link of every state.
+        const uint32_t fail_id = ix->state_bytes == 2 ? 0xffffu : 0xffffffffu;
+        std::vector<uint32_t> go(S * cp), sup(S);
+        for (uint64_t k = 0; k < S; k++) {
+            const uint32_t v = order[k];
+            go[k * cp] = v == 0 ? 0u : fail_id;
+            for (uint32_t c = 0; c < C; c++) {
+                const int32_t w = child[(uint64_t)v * C + c];
+                go[k * cp + 1 + c] = w >= 0 ? newid[w] : (v == 0 ? 0u : fail_id);
+            }
+            sup[k] = newid[supply[v]];
+        }
+        if (ix->state_bytes == 2) {
+            std::vector<uint16_t> g16(go.begin(), go.end()), s16(sup.begin(), sup.end());
+            ix->off_go = put(ix->image, g16.data(), g16.size());
+            ix->sup_off = put(ix->image, s16.data(), s16.size()) - ix->off_go;
+        } else {
+            ix->off_go = put(ix->image, go.data(), go.size());
+            ix->sup_off = put(ix->image, sup.data(), sup.size()) - ix->off_go;
+        }
+        ix->go_bytes = align_up(ix->image.size() - ix->off_go, 16);
+    }
     ix->image.resize(align_up(ix->image.size(), 256), 0);
     return MPM_OK;
 }
@@ -490,13 +516,13 @@ const char *mpm_version(void) { return "mpm 1.0 (gfx950)"; }
 mpm_status mpm_build_ac(const uint8_t *patterns, uint32_t d, uint32_t m, const mpm_opts *opts,
                         mpm_index **out)
 {
-    (void)opts;
     mpm_status st = build_common(patterns, d, m, out, "mpm_build_ac");
     if (st)
         return st;
     try {
         mpm_index *ix = new mpm_index();
         ix->algo = MPM_ALGO_AC;
+        ix->keep_goto = opts && opts->ac_goto ? 1u : 0u;
         ix->m = m;
         ix->d = d;
         dedup(patterns, d, m, ix);
@@ -810,6 +836,9 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             it.hint = r.cost_hint > 0.f ? r.cost_hint : 0.f;
             it.group_hint = 0.f;
             mpm_status st = resolve_variant(r.idx, &v, 0, &it.cfg);
+            if (!st && it.cfg.supply)
+                st = fail(MPM_EUNSUPPORTED, "mpm_batch_plan: the supply-link walk runs in "
+                          "single-text scans only");
             if (st) {
                 delete b;
                 return st;
@@ -1055,6 +1084,8 @@ static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
     mpm_status st = resolve_variant(idx, &w, 0, cfg);
     if (st)
         return st;
+    if (cfg->supply)
+        return fail(MPM_EUNSUPPORTED, "mpm_tune: the supply-link walk runs in single-text scans only");
     const uint64_t tb = (uint64_t)cfg->lane_bytes * cfg->block_threads;
     *nt_copy = (n_starts(n, idx->m) + tb - 1) / tb;
     *idx_off = align_up((uint64_t)copies * sizeof(BatchText), 256);

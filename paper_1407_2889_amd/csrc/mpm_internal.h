@@ -35,6 +35,12 @@ struct AcDev {
     uint32_t n_single;      // distinct strings below this have one id each
     uint32_t hot_states;    // hot placement: rows [0, hot_states) in LDS
     uint32_t hot_bytes;     // bytes of those rows (multiple of 16)
+    // Goto rows (same numbering and columns as the table, all-ones for a
+    // missing transition) followed by the supply link of every state, for
+    // the supply-link walk; go_bytes = 0 when the index has none.
+    const void *go;
+    uint32_t go_bytes;      // goto rows and supply links (multiple of 16)
+    uint32_t sup_off;       // byte offset of the supply links within go
     // Byte classes without a lookup table, usable when the pattern bytes
     // have distinct 3-bit codes (b >> swar_shift) & 7: perm_byte selects, per
     // code, the only byte with that code that is a pattern byte (or a byte
@@ -179,6 +185,9 @@ struct mpm_index {
     // Device image: host copy, offsets, and the caller-owned device buffer.
     std::vector<uint8_t> image;
     uint64_t off_a = 0, off_b = 0, off_c = 0, off_d = 0, off_e = 0, off_f = 0, off_g = 0;
+    // Aho-Corasick goto rows and supply links (kept when asked for)
+    uint32_t keep_goto = 0;
+    uint64_t off_go = 0, go_bytes = 0, sup_off = 0;
     uint64_t table_bytes = 0;
     const uint8_t *d_image = nullptr;
 };
@@ -195,6 +204,7 @@ struct LaunchCfg {
     uint32_t grid;        // resolved workgroup count
     uint32_t lds_bytes;   // dynamic LDS per workgroup
     bool swar;            // AC: byte classes computed in registers
+    bool supply;          // AC: goto function and supply links at run time
     uint32_t ilp;         // virtual lanes per thread (1 or 2)
     uint32_t csr_lds;     // LDS byte offset of the id CSR (0: global memory)
 };

@@ -18,6 +18,9 @@ hipError_t ac16_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd
 const void *ac32_glb_kernel(const LaunchCfg &c);
 const void *ac32_hot_kernel(const LaunchCfg &c);
 hipError_t ac32_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
+const void *ac_supply_kernel(uint32_t state_bytes, const LaunchCfg &c);
+hipError_t ac_supply_launch(uint32_t state_bytes, const AcDev &a, const LaunchCfg &c,
+                            const ScanDev &sd, hipStream_t s);
 hipError_t ac16_lds_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 hipError_t ac16_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
 hipError_t ac32_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s);
@@ -109,6 +112,9 @@ AcDev ac_dev(const mpm_index *ix)
     const uint64_t budget = ((uint64_t)limits().max_lds - 1024u) & ~15ull;
     const uint64_t hb = std::min<uint64_t>(budget, ix->table_bytes);
     a.hot_bytes = (uint32_t)hb;
+    a.go = ix->keep_goto ? (const void *)(ix->d_image + ix->off_go) : nullptr;
+    a.go_bytes = (uint32_t)ix->go_bytes;
+    a.sup_off = (uint32_t)ix->sup_off;
     a.hot_states = (uint32_t)(hb / ((uint64_t)a.cp * ix->state_bytes));
     return a;
 }
@@ -150,6 +156,8 @@ static uint64_t hot_lds_bytes(const mpm_index *ix)
 
 static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
 {
+    if (ix->algo == MPM_ALGO_AC && c.supply)
+        return ac_supply_kernel(ix->state_bytes, c);
     if (ix->algo == MPM_ALGO_AC) {
         if (ix->state_bytes == 4)  // tables of 2^16 states or more never fit whole in LDS
             return c.placement == MPM_PLACE_HOT ? ac32_hot_kernel(c) : ac32_glb_kernel(c);
@@ -182,14 +190,22 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
         return fail(MPM_EINVAL, "variant: block_threads=%u must be 256, 512 or 1024", W);
     if (d.placement > MPM_PLACE_HOT)
         return fail(MPM_EINVAL, "variant: unknown placement %u", d.placement);
+    if (d.flags & ~(MPM_VARIANT_NO_SWAR | MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY))
+        return fail(MPM_EINVAL, "variant: unknown flags 0x%x", d.flags);
+    const bool supply = ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_SUPPLY);
+    if (supply && !ix->keep_goto)
+        return fail(MPM_EUNSUPPORTED, "variant: the supply-link walk needs an index built with "
+                    "ac_goto set");
+    if (supply && (d.flags & MPM_VARIANT_ILP2))
+        return fail(MPM_EUNSUPPORTED, "variant: the supply-link walk has one chain per lane");
     const DeviceLimits lim = limits();
     // dynamic LDS: the kernels' fixed header and byte-class regions, then the
     // tables when they are placed in LDS
     const uint32_t fixed = 1024u;
-    const uint64_t table_lds = fixed + ix->table_bytes;
+    const uint64_t table_lds = fixed + (supply ? ix->go_bytes : ix->table_bytes);
     const bool fits = table_lds <= (uint64_t)lim.max_lds;
     const bool ilp2 = ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2);
-    const bool hot_ok = has_hot(ix) && !ilp2;
+    const bool hot_ok = has_hot(ix) && !ilp2 && !supply;
     uint32_t place = d.placement;
     if (place == MPM_PLACE_AUTO)
         place = fits ? MPM_PLACE_LDS : (hot_ok ? MPM_PLACE_HOT : MPM_PLACE_GLOBAL);
@@ -202,9 +218,12 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     cfg->lane_bytes = L;
     cfg->block_threads = W;
     cfg->placement = place;
-    cfg->swar = ix->algo == MPM_ALGO_AC && ix->swar_ok && !(d.flags & MPM_VARIANT_NO_SWAR);
+    cfg->supply = supply;
+    cfg->swar = ix->algo == MPM_ALGO_AC && ix->swar_ok && !(d.flags & MPM_VARIANT_NO_SWAR) &&
+                !supply;
     cfg->ilp = (ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2)) ? 2 : 1;
-    cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS   ? (uint32_t)ix->table_bytes
+    cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS   ? (uint32_t)(supply ? ix->go_bytes
+                                                                           : ix->table_bytes)
                               : place == MPM_PLACE_HOT ? (uint32_t)hot_lds_bytes(ix)
                                                        : 0u);
     cfg->csr_lds = 0;
@@ -248,7 +267,9 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
     if (c.lds_bytes > 65536)
         (void)hipFuncSetAttribute(kernel_for(ix, c), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)c.lds_bytes);
-    if (ix->algo == MPM_ALGO_AC) {
+    if (ix->algo == MPM_ALGO_AC && c.supply) {
+        e = ac_supply_launch(ix->state_bytes, ac_dev(ix), c, sd, s);
+    } else if (ix->algo == MPM_ALGO_AC) {
         const AcDev a = ac_dev(ix);
         if (ix->state_bytes == 4)
             e = c.placement == MPM_PLACE_HOT ? ac32_hot_launch(a, c, sd, s) : ac32_glb_launch(a, c, sd, s);

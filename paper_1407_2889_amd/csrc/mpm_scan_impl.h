@@ -923,6 +923,103 @@ struct AcWalk {
 };
 
 // ---------------------------------------------------------------------------
+// Aho-Corasick with the goto function and supply links at run time
+// ---------------------------------------------------------------------------
+// The search of Algorithm 3 as the paper's kernels run it (Section 4.2): a
+// transition the goto function lacks follows supply links until a state has
+// one (the root has one for every byte), one byte at a time. It gives the
+// flattened walk's result and is kept to measure what flattening buys. The
+// goto rows use the flattened table's numbering and byte-offset columns; a
+// missing transition is all ones. Supply strictly lowers the depth, so a
+// byte follows at most m links: the loop is bounded by m as well.
+template <typename St, int P>
+struct AcSupplyWalk {
+    using Dev = AcDev;
+    static constexpr int ILP = 1;
+    static constexpr bool InLds = P == PL_LDS;
+    static constexpr uint32_t FAIL = sizeof(St) == 2 ? 0xffffu : 0xffffffffu;
+    typename TabPtr<InLds, uint8_t>::type gob;  // goto rows, addressed in bytes
+    typename TabPtr<InLds, St>::type sup;       // supply link per state
+    lds_cptr<uint16_t> cls;                     // column byte offset per byte value
+    uint32_t rowb, first_term, m;
+
+    template <int W>
+    __device__ __forceinline__ static void load(const AcDev &a)
+    {
+        copy_to_lds<W>(LDS_CLS_OFF, a.cls, 512);
+        if (InLds)
+            copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.go, a.go_bytes);
+    }
+
+    __device__ __forceinline__ void bind(const AcDev &a)
+    {
+        rowb = a.cp * (uint32_t)sizeof(St);
+        first_term = a.first_term;
+        m = a.m;
+        cls = lds_at<const uint16_t>(LDS_CLS_OFF);
+        if constexpr (InLds)
+            gob = lds_at<const uint8_t>(LDS_TAB_OFF);
+        else
+            gob = (glb_cptr<uint8_t>)a.go;
+        sup = (typename TabPtr<InLds, St>::type)(gob + a.sup_off);
+    }
+
+    template <int W>
+    __device__ __forceinline__ void setup(const AcDev &a, uint32_t /*unused*/)
+    {
+        load<W>(a);
+        bind(a);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ uint32_t go(uint32_t s, uint32_t coloff) const
+    {
+        return *(typename TabPtr<InLds, St>::type)(gob + s * rowb + coloff);
+    }
+
+    // One byte: goto, else supply links until a goto exists.
+    __device__ __forceinline__ uint32_t step(uint32_t s, uint32_t coloff) const
+    {
+        uint32_t t = go(s, coloff);
+        for (uint32_t k = 0; t == FAIL && k < m; ++k) {
+            s = sup[s];
+            t = go(s, coloff);
+        }
+        return t == FAIL ? 0u : t;
+    }
+
+    template <class F>
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        if (lo >= hi)
+            return;
+        uint64_t end = base + hi + m - 1;
+        if (end > n)
+            end = n;
+        uint32_t s = 0;
+        auto one = [&](uint32_t b, uint64_t q) {
+            s = step(s, cls[b]);
+            if (s >= first_term)
+                cb(q + 1 - m, s - first_term);
+        };
+        stream_text(text, base + lo, end, one, [&](const v4u c, uint64_t q) {
+            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                one((w[j >> 2] >> (8 * (j & 3))) & 0xffu, q + j);
+        });
+    }
+
+    template <class F>
+    __device__ __forceinline__ void lane_again(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                               uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        lane(text, n, base, lo, hi, cb);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Wu-Manber walker
 // ---------------------------------------------------------------------------
 static const int WM_QUEUE = 4;  // filtered candidates kept before exact checks
@@ -1185,7 +1282,9 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
     // Phase C: ordered writes.
 #pragma unroll
     for (int v = 0; v < I; ++v) {
-        if (nu[v] == 0)
+        // nothing to write: no occurrences, or all of them past the capacity
+        // (a counting call with capacity 0 walks each range once)
+        if (nu[v] == 0 || ob[v] >= cap)
             continue;
         uint64_t o = ob[v];
 #pragma unroll

@@ -203,3 +203,27 @@ def test_placement_resolution():
     with pytest.raises(mpm.MpmError) as e:
         mpm.workspace_bytes(ix, 1 << 20, mpm.variant(64, 256, 4))
     assert e.value.status == mpm.MPM_EINVAL
+
+
+def test_supply_walk_variant_resolution():
+    """The goto + supply-link walk needs an index that kept the goto function;
+    it has one chain per lane and no hot placement; unknown flags are
+    refused. Host-only."""
+    rng = np.random.default_rng(23)
+    P = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, (50, 8))]
+    sup = mpm.VARIANT_SUPPLY
+    plain, withgo = mpm.build_ac(P), mpm.build_ac(P, goto=True)
+    assert withgo.info()["device_bytes"] > plain.info()["device_bytes"]
+    assert withgo.info()["table_bytes"] == plain.info()["table_bytes"]
+    with pytest.raises(mpm.MpmError) as e:
+        mpm.workspace_bytes(plain, 1 << 20, mpm.variant(64, 256, mpm.PLACE_AUTO, 0, sup))
+    assert e.value.status == mpm.MPM_EUNSUPPORTED
+    for pl in (mpm.PLACE_AUTO, mpm.PLACE_LDS, mpm.PLACE_GLOBAL):
+        assert mpm.workspace_bytes(withgo, 1 << 20, mpm.variant(64, 256, pl, 0, sup)) > 0
+    for pl, fl in ((mpm.PLACE_HOT, sup), (mpm.PLACE_AUTO, sup | mpm.VARIANT_ILP2)):
+        with pytest.raises(mpm.MpmError) as e:
+            mpm.workspace_bytes(withgo, 1 << 20, mpm.variant(64, 256, pl, 0, fl))
+        assert e.value.status == mpm.MPM_EUNSUPPORTED
+    with pytest.raises(mpm.MpmError) as e:
+        mpm.workspace_bytes(withgo, 1 << 20, mpm.variant(64, 256, 0, 0, 8))
+    assert e.value.status == mpm.MPM_EINVAL

@@ -249,3 +249,27 @@ def test_per_pattern_counts_edges(mpm):
         say(f"[counts] d={d} M={M}")
         got = mpm.count_ids(dev, d).cpu().numpy().view(np.uint32)
         assert np.array_equal(got, np.bincount(ids[ids < d], minlength=d)), (d, M)
+
+
+@pytest.mark.parametrize("case", ["small", "est", "u32"])
+def test_supply_walk(mpm, small, case):
+    """The goto function with supply links at run time (the paper's kernel
+    design) against the oracle: tables in LDS and in global memory, 16- and
+    32-bit states, several launch shapes, text offsets 0 and 3."""
+    if case == "small":
+        t, P, want = small
+    else:
+        t = synth.est_text(2_000_000, seed=61)
+        d, m = (1000, 16) if case == "est" else (6000, 20)
+        P = synth.pattern_set(t, d=d, m=m, n_planted=d // 3, seed=62).patterns
+        want = oracle.Win(P).scan(t)
+    ix = mpm.build_ac(P, upload=True, goto=True)
+    assert ix.info()["state_bytes"] == (4 if case == "u32" else 2)
+    sup = mpm.VARIANT_SUPPLY
+    for mis in (0, 3):
+        for v in (dict(lane_bytes=64, block_threads=256, placement=mpm.PLACE_AUTO, flags=sup),
+                  dict(lane_bytes=1024, block_threads=1024, placement=mpm.PLACE_GLOBAL, flags=sup),
+                  dict(lane_bytes=16, block_threads=512, placement=mpm.PLACE_AUTO, flags=sup)):
+            say(f"[supply] {case} misalign={mis} {v}")
+            got = gpu_pairs(mpm, ix, t, mpm.variant(**v), misalign=mis)
+            assert_same(got, want, f"supply {case} mis={mis} {v}")
