@@ -107,17 +107,23 @@ def edge_cases():
 
 
 @pytest.mark.parametrize("case", edge_cases(), ids=lambda c: c[0])
-@pytest.mark.parametrize("algo", ["ac", "wm"])
+@pytest.mark.parametrize("algo", ["ac", "wm", "ac-supply"])
 def test_edge_cases(mpm, case, algo):
     name, T, P = case
     want = oracle.Win(P).scan(T)
     assert_same(oracle.AC(P).scan(T), want, "oracle AC")
-    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    if algo == "wm":
+        ix = mpm.build_wm(P, upload=True)
+    else:
+        ix = mpm.build_ac(P, upload=True, goto=algo == "ac-supply")
+    variants = (dict(lane_bytes=16, block_threads=256), dict(lane_bytes=64, block_threads=1024),
+                dict(lane_bytes=256, block_threads=512, placement=2),
+                dict(lane_bytes=32, block_threads=256, flags=2),
+                dict(lane_bytes=128, block_threads=1024, flags=3))
+    if algo == "ac-supply":
+        variants = tuple(dict(v, flags=mpm.VARIANT_SUPPLY) for v in variants if not v.get("flags"))
     for mis in (0, 3):
-        for v in (dict(lane_bytes=16, block_threads=256), dict(lane_bytes=64, block_threads=1024),
-                  dict(lane_bytes=256, block_threads=512, placement=2),
-                  dict(lane_bytes=32, block_threads=256, flags=2),
-                  dict(lane_bytes=128, block_threads=1024, flags=3)):
+        for v in variants:
             say(f"[edge {name} n={len(T)} d={len(P)} m={P.shape[1]}] {algo} misalign={mis} {v}")
             got = gpu_pairs(mpm, ix, T, mpm.variant(**v), misalign=mis)
             assert_same(got, want, f"{name} {algo} mis={mis} {v}")
@@ -273,3 +279,19 @@ def test_supply_walk(mpm, small, case):
             say(f"[supply] {case} misalign={mis} {v}")
             got = gpu_pairs(mpm, ix, t, mpm.variant(**v), misalign=mis)
             assert_same(got, want, f"supply {case} mis={mis} {v}")
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_persistent_grid_sizes(mpm, small, algo):
+    """The same list whatever the number of persistent workgroups taking
+    chunk tickets (one workgroup walking every chunk in turn, a few, a
+    prime number, more than the chunks), repeated on one workspace."""
+    text, P, want = small
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    t = to_dev(text)
+    for grid in (1, 3, 17, 256, 4096):
+        v = mpm.variant(lane_bytes=64, block_threads=256, grid=grid)
+        sc = mpm.Scanner(ix, len(text), capacity=len(want[0]) + 16, var=v)
+        for rep in range(3):
+            say(f"[grid] {algo} grid={grid} rep={rep}")
+            assert_same(mpm.pairs_numpy(sc.scan(t)), want, f"{algo} grid={grid} rep={rep}")
