@@ -305,6 +305,35 @@ def run_ablation(args):
     print(json.dumps(line), flush=True)
 
 
+def run_scaling(args):
+    """Kernel time against the number of busy CUs: the AC and WM scans of the
+    first k MiB of the 256 MiB EST text in the benchmark's launch
+    configuration (one 1 MiB chunk per workgroup, one workgroup per CU), k
+    from 1 to 256. One JSON line."""
+    import torch
+    import paper_1407_2889_amd as mpm
+    text, ps, desc = workload("est256")
+    dev = torch.from_numpy(text).cuda()
+    stream = torch.cuda.current_stream()
+    rows = []
+    for algo in ("ac", "wm"):
+        ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(ps.patterns, upload=True)
+        v = mpm.variant(**DEFAULT_VARIANTS[algo])
+        for k in (1, 8, 64, 128, 192, 256):
+            n = min(len(text), k << 20)
+            sc = mpm.Scanner(ix, n, capacity=1 << 16, var=v)
+            kms = time_scans(sc, dev[:n], args.steps, args.warmup, stream)
+            rows.append({"algo": algo, "chunks": k, "kernel_us": round(kms * 1e3, 2),
+                         "gbps": round(n / (kms * 1e-3) / 1e9, 2)})
+            log(f"[bench] scaling {algo} {k} chunks: {rows[-1]['kernel_us']} us")
+            del sc
+        del ix
+    line = {"metric": "kernel time against busy CUs", "workload": "scaling",
+            "config": {"workload": desc, "variants": DEFAULT_VARIANTS}, "steps": args.steps,
+            "warmup": args.warmup, "dtype": "u8", "data": "synthetic", "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def run_batched(args):
     """Batched workload with variant selection: a timing database of seeded
     training requests, the selector trained on it, then the 4,096-text batch
@@ -383,6 +412,8 @@ def main():
         return run_stream(args)
     if args.workload == "ablation":
         return run_ablation(args)
+    if args.workload == "scaling":
+        return run_scaling(args)
 
     import torch
     import paper_1407_2889_amd as mpm
