@@ -9,7 +9,8 @@ windows + 700 random; seed 3). Inputs are resident in HBM before timing.
 Prints one JSON line. `value` is whole-step text throughput: 2 n bytes
 scanned (n by AC, n by WM) per second. The line also carries the roofline of
 the dominant kernel (HIP events on the launch stream) and the CPU oracle's
-throughput on the same text (host threads, up to 16).
+throughput on the same text (one thread per usable host CPU, at most one
+GPU's share of the host: 16).
 
 Other workloads (one JSON line each):
   --workload sweep   1 GiB EST-shaped text against nine pattern sets
@@ -92,14 +93,30 @@ def workload(name: str):
     return text, ps, desc
 
 
+# Host threads one GPU's share of the GPU host gives a process (the host runs
+# one such share per GPU, whatever the operating system reports as online).
+HOST_SHARE_THREADS = 16
+
+
+def host_cpus() -> dict:
+    """What the host reports: online CPUs, CPUs this process may run on."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = os.cpu_count() or 1
+    return {"online": os.cpu_count() or 1, "affinity": aff}
+
+
 def cpu_baseline(text, P, sample_bytes: int):
     """The CPU oracle (literal AC and WM, as written) on the host cores: the
     text split into contiguous ranges with the m - 1 overlap (the paper's
-    split) on a thread pool of up to 16 threads; single-thread rates of a
+    split between nodes, Section 4.4) on one thread per CPU this process may
+    use, capped at one GPU's share of the host; single-thread rates of a
     smaller prefix are given in `sample`."""
     import oracle
     s = text[:sample_bytes]
-    workers = max(1, min(16, os.cpu_count() or 1))
+    cpus = host_cpus()
+    workers = max(1, min(HOST_SHARE_THREADS, cpus["affinity"]))
     ac, wm = oracle.AC(P), oracle.WM(P)
     t0 = time.perf_counter()
     oracle.parallel_scan(ac, s, workers=workers)
@@ -116,6 +133,8 @@ def cpu_baseline(text, P, sample_bytes: int):
         "value": round(2 * len(s) / (t2 - t0) / 1e9, 5),
         "unit": "GB/s",
         "cores": workers,
+        "host_cpus_online": cpus["online"],
+        "host_cpus_affinity": cpus["affinity"],
         "kind": "oracle",
         "sample": f"first {len(s)} bytes of the same text on {workers} threads (contiguous "
                   f"ranges with the m-1 overlap): oracle AC (Algorithms 1-3) "
@@ -344,7 +363,7 @@ def run_batched(args):
     from paper_1407_2889_amd import learn, selection, tune
     t_start = time.perf_counter()
     log(f"[bench] timing database: {args.train_requests} requests")
-    stream, sets, reqs = selection.training_requests(args.train_requests, 48, seed=1000,
+    stream, sets, reqs = synth.selector_training_requests(args.train_requests, 48, seed=1000,
                                                      stream_bytes=256 << 20)
     sd = torch.from_numpy(stream).cuda()
     sidx = [tune.PatternSetIndexes.build(p.patterns) for p in sets]

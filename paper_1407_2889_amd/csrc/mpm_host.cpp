@@ -131,7 +131,7 @@ static mpm_status build_ac_tables(mpm_index *ix)
     for (int b = 0; b < 256; b++)
         if (present[b]) {
             ix->class_bytes[C] = (uint8_t)b;
-            ix->cls[b] = (uint8_t)(C + 1);
+            ix->cls[b] = (uint16_t)(C + 1);
             C++;
         }
     ix->n_classes = C;
@@ -650,6 +650,28 @@ mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids
 
 static uint64_t n_starts(uint64_t n, uint32_t m) { return n >= m ? n - m + 1 : 0; }
 
+}  // extern "C"
+
+// Bounds of the kernels' counters: a lane counts its ids in 32 bits and a
+// wave's prefix sum over its 64 lanes stays in 32 bits (at most
+// 64 * lane_bytes * max_dup ids); a look-back status word carries a text's
+// inclusive count in ST_VAL_BITS bits (at most ns * max_dup ids).
+static mpm_status check_counts(const mpm_index *ix, uint64_t ns, uint32_t lane_bytes,
+                               const char *who)
+{
+    const uint64_t md = ix->max_dup ? ix->max_dup : 1;
+    if (64ull * lane_bytes * md >= (1ull << 32))
+        return fail(MPM_EUNSUPPORTED, "%s: %u copies of one pattern overflow a wave's 32-bit "
+                    "count at %u starting positions per lane", who, ix->max_dup, lane_bytes);
+    if (ns * md >= (1ull << ST_VAL_BITS))
+        return fail(MPM_ETOOBIG, "%s: %llu starting positions x %u copies of one pattern "
+                    "exceed the %u-bit count of a text", who, (unsigned long long)ns, ix->max_dup,
+                    (unsigned)ST_VAL_BITS);
+    return MPM_OK;
+}
+
+extern "C" {
+
 mpm_status mpm_workspace_bytes(const mpm_index *idx, uint64_t n, const mpm_variant *v,
                                uint64_t *bytes)
 {
@@ -671,8 +693,6 @@ mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm
 {
     if (!idx || !d_total || !d_work)
         return fail(MPM_EINVAL, "mpm_scan: null index, workspace or total");
-    if (!idx->d_image)
-        return fail(MPM_ESTATE, "mpm_scan: index not uploaded (call mpm_upload)");
     if (n >= (1ull << 32))
         return fail(MPM_ETOOBIG, "mpm_scan: n = %llu needs 32-bit positions",
                     (unsigned long long)n);
@@ -689,9 +709,11 @@ mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm
         return st;
     uint64_t tb = tile_bytes(cfg);
     uint64_t nt = (ns + tb - 1) / tb;
-    if (tb * (uint64_t)idx->max_dup >= (1ull << ST_VAL_BITS))
-        return fail(MPM_EUNSUPPORTED, "mpm_scan: %u copies of one pattern overflow a chunk count",
-                    idx->max_dup);
+    st = check_counts(idx, ns, cfg.lane_bytes, "mpm_scan");
+    if (st)
+        return st;
+    if (!idx->d_image)
+        return fail(MPM_ESTATE, "mpm_scan: index not uploaded (call mpm_upload)");
     if (work_bytes < WS_HEADER_BYTES + 8 * nt)
         return fail(MPM_ENOMEM, "mpm_scan: workspace of %llu bytes, need %llu",
                     (unsigned long long)work_bytes, (unsigned long long)(WS_HEADER_BYTES + 8 * nt));
@@ -843,10 +865,10 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 delete b;
                 return st;
             }
-            if ((uint64_t)it.cfg.lane_bytes * it.cfg.block_threads * r.idx->max_dup >=
-                (1ull << ST_VAL_BITS)) {
+            st = check_counts(r.idx, n_starts(r.n, r.idx->m), it.cfg.lane_bytes, "mpm_batch_plan");
+            if (st) {
                 delete b;
-                return fail(MPM_EUNSUPPORTED, "mpm_batch_plan: too many copies of one pattern");
+                return st;
             }
             it.kind = batch_kind(r.idx, it.cfg);
             const auto key = std::make_tuple(it.kind, it.cfg.block_threads, lds_class(it.cfg.lds_bytes));
@@ -1125,6 +1147,9 @@ mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n
     if (work_bytes < bytes)
         return fail(MPM_ENOMEM, "mpm_tune_time: workspace of %llu bytes, need %llu",
                     (unsigned long long)work_bytes, (unsigned long long)bytes);
+    st = check_counts(idx, n_starts(n, idx->m), cfg.lane_bytes, "mpm_tune_time");
+    if (st)
+        return st;
     if (nt == 0) {
         *ms_out = 0.f;
         return MPM_OK;

@@ -168,7 +168,7 @@ struct mpm_index {
     // Aho-Corasick
     uint32_t n_classes = 0;
     uint8_t class_bytes[256] = {0};
-    uint8_t cls[256] = {0};
+    uint16_t cls[256] = {0};         // byte -> 1 + class (0: in no pattern); up to 256 classes
     uint32_t swar_ok = 0, swar_shift = 0;
     uint8_t perm_byte[8] = {0}, perm_col[8] = {0};
     uint64_t n_states = 0;

@@ -18,29 +18,9 @@ import time
 
 import numpy as np
 
-import synth
-
 from . import batch as _batch
 from . import tune
 from .learn import Selector
-
-
-def training_requests(n_req: int, n_sets: int, seed: int, stream_bytes: int = 256 << 20,
-                      max_len: int = 4 << 20, d_hi: int = 50000):
-    """Seeded requests for the timing database: text slices of one EST-shaped
-    stream (256-byte aligned starts) paired with a pool of pattern sets."""
-    lens, ds, ms = synth.batch_request_shapes(n_req, n_sets, seed, seed + 1, max_len=max_len,
-                                              d_hi=d_hi)
-    stream = synth.est_text(stream_bytes, seed=seed + 2)
-    rng = np.random.default_rng(seed + 3)
-    offs = (rng.integers(0, stream_bytes - lens + 1) // 256 * 256).astype(np.int64)
-    pair = rng.integers(0, n_sets, n_req)
-    sets = []
-    for k in range(n_sets):
-        d = int(ds[k])
-        sets.append(synth.pattern_set(stream, d=d, m=int(ms[k]), n_planted=d // 10,
-                                      seed=seed + 100 + k))
-    return stream, sets, list(zip(pair.tolist(), offs.tolist(), lens.tolist()))
 
 
 def build_db(tuner: tune.Tuner, sets_idx, stream_dev, reqs, log=None):
@@ -109,9 +89,11 @@ def run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps: int = 5):
     return tms, bs.totals_host(), bs.groups
 
 
-def evaluate(b: synth.Batch, tuner: tune.Tuner, selector: Selector, default_variant: int,
+def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
              margin: float = 0.05, reps: int = 5, log=None):
-    """Run the three policies on batch b; returns a result dict."""
+    """Run the three policies on batch b (texts, pattern sets and the set of
+    each text: ``b.texts``, ``b.sets[k].patterns``, ``b.pairing``); returns a
+    result dict."""
     sets_idx = [tune.PatternSetIndexes.build(ps.patterns) for ps in b.sets]
     arena, offs, lens = _batch.pack_texts(b.texts)
     R = len(b.texts)

@@ -201,3 +201,24 @@ def workload_batch(n_texts: int = 4096, n_sets: int = 64, max_len: int = 4 * MiB
         sets.append(pattern_set(pool[0], d=d, m=int(ms[k]), n_planted=d // 10,
                                 seed=seed + 100 + k, texts=pool))
     return Batch(texts, sets, pairing, {"lens": lens, "offsets": offs, "stream": stream})
+
+
+def selector_training_requests(n_req: int, n_sets: int, seed: int,
+                                stream_bytes: int = 256 << 20, max_len: int = 4 << 20,
+                                d_hi: int = 50000):
+    """Seeded requests for the variant selector's timing database, drawn from
+    the batched workload's distributions: text slices of one EST-shaped stream
+    (256-byte aligned starts, log-uniform lengths) paired with a pool of
+    pattern sets. Returns (stream, sets, [(set, offset, length), ...])."""
+    lens, ds, ms = batch_request_shapes(n_req, n_sets, seed, seed + 1, max_len=max_len,
+                                        d_hi=d_hi)
+    stream = est_text(stream_bytes, seed=seed + 2)
+    rng = np.random.default_rng(seed + 3)
+    offs = (rng.integers(0, stream_bytes - lens + 1) // 256 * 256).astype(np.int64)
+    pair = rng.integers(0, n_sets, n_req)
+    sets = []
+    for k in range(n_sets):
+        d = int(ds[k])
+        sets.append(pattern_set(stream, d=d, m=int(ms[k]), n_planted=d // 10,
+                                seed=seed + 100 + k))
+    return stream, sets, list(zip(pair.tolist(), offs.tolist(), lens.tolist()))

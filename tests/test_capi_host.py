@@ -120,6 +120,52 @@ def test_ac_table_walk_equals_oracle(seed):
     assert got == list(zip(pos.tolist(), idv.tolist()))
 
 
+@pytest.mark.parametrize("n_bytes", [255, 256])
+def test_ac_over_every_byte_value(n_bytes):
+    """Patterns that use all 256 byte values (256 symbol classes, 257 table
+    columns) build, and the exported table walks to the oracle's list."""
+    rng = np.random.default_rng(n_bytes)
+    vals = rng.permutation(256)[:n_bytes].astype(np.uint8)
+    P = vals[: (n_bytes // 8) * 8].reshape(-1, 8).copy()
+    P = np.concatenate([P, vals[rng.integers(0, n_bytes, (20, 8))]])
+    T = vals[rng.integers(0, n_bytes, 20000)].astype(np.uint8)
+    for k in range(0, 20000 - 8, 997):  # plant occurrences
+        T[k:k + 8] = P[k % len(P)]
+    ix = mpm.build_ac(P)
+    inf = ix.info()
+    assert inf["n_classes"] == len(set(P.flatten().tolist()))
+    table, classes = ix.export_ac()
+    assert table.shape[1] == inf["n_classes"] + 1
+    uoff, ids = ix.export_unique()
+    got = expand(simulate_dfa(table, classes, 8, inf["d_unique"], T), uoff, ids)
+    pos, idv = oracle.Win(P).scan(T)
+    assert len(pos) > 0
+    assert got == list(zip(pos.tolist(), idv.tolist()))
+
+
+def test_count_guards():
+    """Counts the kernels could not hold are refused on the host: a wave's
+    32-bit prefix (64 lanes x lane_bytes x copies of one pattern) and a text's
+    36-bit count (starting positions x copies)."""
+    P = np.zeros((70000, 4), np.uint8)  # one string, 70,000 ids
+    ix = mpm.build_ac(P)
+    assert ix.info()["max_dup"] == 70000
+    tot = C.c_uint64()
+
+    def scan(n, lane_bytes):
+        v = mpm.variant(lane_bytes=lane_bytes, block_threads=256)
+        ws = mpm.workspace_bytes(ix, n, v)
+        return mpm._L.mpm_scan_sync(ix.handle, C.c_void_p(4096), n, None, 0, C.c_void_p(4096),
+                                    ws, C.c_void_p(8), C.byref(v), None, C.byref(tot))
+    # 64 * 1024 * 70,000 >= 2^32: a wave's prefix would overflow
+    assert scan(1 << 20, 1024) == mpm.MPM_EUNSUPPORTED
+    assert b"32-bit" in mpm._L.mpm_last_error()
+    # (2^20 - 3) * 70,000 >= 2^36: the text's count would overflow
+    assert scan(1 << 20, 16) == mpm.MPM_ETOOBIG
+    # within both bounds the request goes on (and stops at the missing upload)
+    assert scan(1 << 19, 16) == mpm.MPM_ESTATE
+
+
 def test_ac_state_count_matches_oracle_trie():
     rng = np.random.default_rng(3)
     P = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, (300, 8))]

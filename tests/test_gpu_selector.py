@@ -26,7 +26,7 @@ def say(*a):
 def test_selector_beats_fixed_variant_on_held_out_batch():
     from paper_1407_2889_amd import learn, selection, tune
     say("[selector] timing database")
-    stream, sets, reqs = selection.training_requests(400, 24, seed=7000, stream_bytes=64 << 20,
+    stream, sets, reqs = synth.selector_training_requests(400, 24, seed=7000, stream_bytes=64 << 20,
                                                      max_len=1 << 20, d_hi=20000)
     sd = torch.from_numpy(stream).cuda()
     sidx = [tune.PatternSetIndexes.build(p.patterns) for p in sets]
