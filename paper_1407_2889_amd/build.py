@@ -35,24 +35,40 @@ def sources() -> list[str]:
     return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
-def build(verbose: bool = False, extra: list[str] | None = None, jobs: int = 8) -> str:
+def _headers() -> list[str]:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    return hs + [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+
+
+def build(verbose: bool = False, extra: list[str] | None = None, jobs: int = 8,
+          incremental: bool = False) -> str:
     """Compile every source (in parallel, one object per source) and link
-    libmpm.so. Always recompiles."""
+    libmpm.so. Recompiles everything unless `incremental`, which keeps the
+    objects in _build/ at the repository root and recompiles a source only
+    when it, or any header, is newer than its object."""
     import concurrent.futures as cf
     import tempfile
     compile_flags = [f for f in FLAGS if f != "-shared"]
+    keep = os.path.join(os.path.dirname(HERE), "_build") if incremental else None
     with tempfile.TemporaryDirectory(prefix="mpm_build_") as td:
+        odir = keep or td
+        os.makedirs(odir, exist_ok=True)
+        newest_h = max((os.path.getmtime(h) for h in _headers()), default=0.0)
         objs = []
         cmds = []
         for src in sources():
-            obj = os.path.join(td, os.path.basename(src) + ".o")
+            obj = os.path.join(odir, os.path.basename(src) + ".o")
             objs.append(obj)
+            if keep and os.path.exists(obj) and os.path.getmtime(obj) > max(
+                    os.path.getmtime(src), newest_h):
+                continue
             cmds.append([HIPCC, *compile_flags, *(extra or []), "-c", src, "-o", obj])
-        with cf.ThreadPoolExecutor(max(1, min(jobs, len(cmds)))) as ex:
-            for cmd in cmds:
-                if verbose:
-                    print(" ".join(cmd), flush=True)
-            list(ex.map(subprocess.check_call, cmds))
+        if cmds:
+            with cf.ThreadPoolExecutor(max(1, min(jobs, len(cmds)))) as ex:
+                for cmd in cmds:
+                    if verbose:
+                        print(" ".join(cmd), flush=True)
+                list(ex.map(subprocess.check_call, cmds))
         tmp = LIB + f".tmp{os.getpid()}"
         link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
         if verbose:
@@ -63,5 +79,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int = 8) 
 
 
 if __name__ == "__main__":
-    build(verbose=True, extra=sys.argv[1:])
+    args = sys.argv[1:]
+    inc = "--incremental" in args
+    build(verbose=True, extra=[a for a in args if a != "--incremental"], incremental=inc)
     print(LIB)

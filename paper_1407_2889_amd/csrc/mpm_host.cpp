@@ -687,21 +687,26 @@ mpm_status mpm_workspace_bytes(const mpm_index *idx, uint64_t n, const mpm_varia
     return MPM_OK;
 }
 
-mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm_match *d_out,
-                    uint64_t capacity, void *d_work, uint64_t work_bytes, uint64_t *d_total,
-                    const mpm_variant *v, void *stream)
+}  // extern "C"
+
+namespace mpm {
+// mpm_scan on a given workspace; `who` names the entry point in errors.
+mpm_status scan_with_workspace(const mpm_index *idx, const uint8_t *d_text, uint64_t n,
+                               mpm_match *d_out, uint64_t capacity, void *d_work,
+                               uint64_t work_bytes, uint64_t *d_total, const mpm_variant *v,
+                               void *stream, const char *who)
 {
     if (!idx || !d_total || !d_work)
-        return fail(MPM_EINVAL, "mpm_scan: null index, workspace or total");
+        return fail(MPM_EINVAL, "%s: null index, workspace or total", who);
     if (n >= (1ull << 32))
-        return fail(MPM_ETOOBIG, "mpm_scan: n = %llu needs 32-bit positions",
+        return fail(MPM_ETOOBIG, "%s: n = %llu needs 32-bit positions", who,
                     (unsigned long long)n);
     if (capacity && !d_out)
-        return fail(MPM_EINVAL, "mpm_scan: d_out is NULL with capacity > 0");
+        return fail(MPM_EINVAL, "%s: d_out is NULL with capacity > 0", who);
     if (n && !d_text)
-        return fail(MPM_EINVAL, "mpm_scan: d_text is NULL");
+        return fail(MPM_EINVAL, "%s: d_text is NULL", who);
     if (((uintptr_t)d_work) & 7)
-        return fail(MPM_EINVAL, "mpm_scan: workspace must be 8-byte aligned");
+        return fail(MPM_EINVAL, "%s: workspace must be 8-byte aligned", who);
     LaunchCfg cfg;
     uint64_t ns = n_starts(n, idx->m);
     mpm_status st = resolve_variant(idx, v, 0, &cfg);
@@ -709,13 +714,13 @@ mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm
         return st;
     uint64_t tb = tile_bytes(cfg);
     uint64_t nt = (ns + tb - 1) / tb;
-    st = check_counts(idx, ns, cfg.lane_bytes, "mpm_scan");
+    st = check_counts(idx, ns, cfg.lane_bytes, who);
     if (st)
         return st;
     if (!idx->d_image)
-        return fail(MPM_ESTATE, "mpm_scan: index not uploaded (call mpm_upload)");
+        return fail(MPM_ESTATE, "%s: index not uploaded (call mpm_upload)", who);
     if (work_bytes < WS_HEADER_BYTES + 8 * nt)
-        return fail(MPM_ENOMEM, "mpm_scan: workspace of %llu bytes, need %llu",
+        return fail(MPM_ENOMEM, "%s: workspace of %llu bytes, need %llu", who,
                     (unsigned long long)work_bytes, (unsigned long long)(WS_HEADER_BYTES + 8 * nt));
     if (nt == 0)
         return launch_zero_totals(nullptr, 0, d_total, stream);
@@ -738,6 +743,17 @@ mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm
     sd.hdr = (uint32_t *)d_work;
     sd.status = (uint64_t *)((uint8_t *)d_work + WS_HEADER_BYTES);
     return launch_scan(idx, cfg, sd, stream);
+}
+}  // namespace mpm
+
+extern "C" {
+
+mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm_match *d_out,
+                    uint64_t capacity, void *d_work, uint64_t work_bytes, uint64_t *d_total,
+                    const mpm_variant *v, void *stream)
+{
+    return scan_with_workspace(idx, d_text, n, d_out, capacity, d_work, work_bytes, d_total, v,
+                               stream, "mpm_scan");
 }
 
 mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n, mpm_match *d_out,

@@ -103,6 +103,11 @@ def edge_cases():
     bytes_all = rng.integers(0, 256, 40_000).astype(np.uint8)
     P = np.stack([bytes_all[s:s + 5] for s in rng.integers(0, 40_000 - 5, 30)])
     cases.append(("binary alphabet", bytes_all, P))
+    # every byte value is a pattern byte: 256 symbol classes
+    t = rng.integers(0, 256, 60_000).astype(np.uint8)
+    P = np.concatenate([rng.permutation(256).astype(np.uint8).reshape(32, 8),
+                        np.stack([t[s:s + 8] for s in rng.integers(0, 60_000 - 8, 40)])])
+    cases.append(("all 256 byte values", t, P))
     return cases
 
 
