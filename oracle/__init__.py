@@ -10,6 +10,9 @@ Wu-Manber per Algorithms 4-5). This module compiles it with gcc, loads it with
 ctypes and adds numpy conveniences. ``mlp.py`` holds the FP64 reference of the
 variant-selector network.
 
+Pattern sets are a ``uint8 [d, m]`` array (equal lengths, as in the paper) or
+a list of byte strings, which may differ in length.
+
 All scans return ``(pos, id)`` as two uint32 arrays in ascending (pos, id)
 order. Range scans cover start positions ``[lo, hi)``; ``parallel_scan`` splits
 a text into contiguous ranges (the paper's split, Section 4.4) and concatenates
@@ -54,10 +57,23 @@ def lib():
             build()
             L = C.CDLL(_LIB)
             u64, u32, vp = C.c_uint64, C.c_uint32, C.c_void_p
+            u64p = C.POINTER(C.c_uint64)
             L.orc_bf.restype = u64
             L.orc_bf.argtypes = [u8p, u64, u8p, u32, u32, u64, u64, u32p, u32p, u64]
+            L.orc_bf_v.restype = u64
+            L.orc_bf_v.argtypes = [u8p, u64, u8p, u64p, u32, u64, u64, u32p, u32p, u64]
             L.orc_win_build.restype = vp
             L.orc_win_build.argtypes = [u8p, u32, u32]
+            L.orc_win_build_v.restype = vp
+            L.orc_win_build_v.argtypes = [u8p, u64p, u32]
+            L.orc_ac_build_v.restype = vp
+            L.orc_ac_build_v.argtypes = [u8p, u64p, u32]
+            L.orc_wm_build_v.restype = vp
+            L.orc_wm_build_v.argtypes = [u8p, u64p, u32, u32, u32, u32]
+            L.orc_ac_nout_all.restype = u32
+            L.orc_ac_nout_all.argtypes = [vp, u64]
+            L.orc_ac_out_all.restype = u32
+            L.orc_ac_out_all.argtypes = [vp, u64, u32]
             L.orc_win_free.argtypes = [vp]
             L.orc_win_scan.restype = u64
             L.orc_win_scan.argtypes = [vp, u8p, u64, u64, u64, u32p, u32p, u64]
@@ -111,16 +127,38 @@ def _ptr(a: np.ndarray, t=u8p):
     return a.ctypes.data_as(t)
 
 
-def _patterns(P) -> tuple[np.ndarray, int, int]:
-    if isinstance(P, (list, tuple)):
-        if len(P) == 0:
-            return np.zeros((0, 0), np.uint8), 0, 0
-        m = len(P[0])
-        assert all(len(p) == m for p in P), "all patterns must have the same length"
-        P = np.frombuffer(b"".join(bytes(p) for p in P), dtype=np.uint8).reshape(len(P), m)
-    P = np.ascontiguousarray(P, dtype=np.uint8)
-    assert P.ndim == 2
-    return P, P.shape[0], P.shape[1]
+class PatternSet:
+    """d patterns as one byte array and offsets: pattern r is
+    bytes[off[r]:off[r + 1]]. m is the common length, or None when lengths
+    differ."""
+
+    def __init__(self, P):
+        if isinstance(P, PatternSet):
+            self.__dict__.update(P.__dict__)
+            return
+        if isinstance(P, (list, tuple)):
+            pats = [bytes(p) for p in P]
+            assert all(len(p) > 0 for p in pats), "patterns must be non-empty"
+            self.bytes = np.frombuffer(b"".join(pats) or b"\0", np.uint8)
+            self.lengths = np.array([len(p) for p in pats], np.uint64)
+        else:
+            A = np.ascontiguousarray(P, dtype=np.uint8)
+            assert A.ndim == 2
+            self.bytes = A.reshape(-1) if A.size else np.zeros(1, np.uint8)
+            self.lengths = np.full(A.shape[0], A.shape[1], np.uint64)
+        self.d = len(self.lengths)
+        self.off = np.zeros(self.d + 1, np.uint64)
+        self.off[1:] = np.cumsum(self.lengths)
+        lens = set(self.lengths.tolist())
+        self.m = int(next(iter(lens))) if len(lens) == 1 else None
+        self.shortest = int(self.lengths.min()) if self.d else 0
+        self.longest = int(self.lengths.max()) if self.d else 0
+
+    def pattern(self, r: int) -> bytes:
+        return self.bytes[int(self.off[r]):int(self.off[r + 1])].tobytes()
+
+    def args(self):
+        return _ptr(self.bytes), self.off.ctypes.data_as(C.POINTER(C.c_uint64)), self.d
 
 
 def _run(fn, cap_guess: int):
@@ -146,13 +184,12 @@ def bf(text, P, lo: int = 0, hi: int | None = None):
     """Brute force over the definition (Section 1). Small inputs only."""
     L = lib()
     T = _u8(text)
-    P, d, m = _patterns(P)
+    ps = PatternSet(P)
     n = len(T)
     hi = n if hi is None else hi
     Tp = T if n else np.zeros(1, np.uint8)
-    Pp = P if P.size else np.zeros(1, np.uint8)
-    return _run(lambda p, i, c: L.orc_bf(_ptr(Tp), n, _ptr(Pp), d, m, lo, hi,
-                                         _ptr(p, u32p), _ptr(i, u32p), c),
+    return _run(lambda p, i, c: L.orc_bf_v(_ptr(Tp), n, *ps.args(), lo, hi,
+                                           _ptr(p, u32p), _ptr(i, u32p), c),
                 _cap_guess(lo, hi, n))
 
 
@@ -186,11 +223,10 @@ class Win(_Handle):
 
     def __init__(self, P):
         L = lib()
-        P, d, m = _patterns(P)
-        self.d, self.m = d, m
-        Pp = P if P.size else np.zeros(1, np.uint8)
+        ps = PatternSet(P)
+        self.ps, self.d, self.m = ps, ps.d, ps.m
         type(self)._free = L.orc_win_free
-        super().__init__(L.orc_win_build(_ptr(Pp), d, m), P)
+        super().__init__(L.orc_win_build_v(*ps.args()), ps)
 
     def scan(self, text, lo: int = 0, hi: int | None = None):
         L = lib()
@@ -208,11 +244,10 @@ class AC(_Handle):
 
     def __init__(self, P):
         L = lib()
-        P, d, m = _patterns(P)
-        self.d, self.m = d, m
-        Pp = P if P.size else np.zeros(1, np.uint8)
+        ps = PatternSet(P)
+        self.ps, self.d, self.m = ps, ps.d, ps.m
         type(self)._free = L.orc_ac_free
-        super().__init__(L.orc_ac_build(_ptr(Pp), d, m), P)
+        super().__init__(L.orc_ac_build_v(*ps.args()), ps)
 
     @property
     def nstates(self) -> int:
@@ -228,8 +263,15 @@ class AC(_Handle):
         return int(lib().orc_ac_depth(self.h, q))
 
     def output(self, q: int) -> list[int]:
+        """Patterns whose own path ends at state q (Algorithm 1)."""
         L = lib()
         return [int(L.orc_ac_out(self.h, q, k)) for k in range(L.orc_ac_nout(self.h, q))]
+
+    def output_all(self, q: int) -> list[int]:
+        """The merged output set of q: every pattern that is a suffix of the
+        state's label (its own patterns and those of its supply chain)."""
+        L = lib()
+        return [int(L.orc_ac_out_all(self.h, q, k)) for k in range(L.orc_ac_nout_all(self.h, q))]
 
     def trace(self, text, lo: int = 0, hi: int | None = None) -> np.ndarray:
         T = _u8(text)
@@ -255,14 +297,15 @@ class WM(_Handle):
 
     def __init__(self, P, B: int = 3, Bp: int = 2, bitshift: int = 2):
         L = lib()
-        P, d, m = _patterns(P)
-        self.d, self.m, self.B, self.Bp, self.bitshift = d, m, B, Bp, bitshift
-        Pp = P if P.size else np.zeros(1, np.uint8)
-        h = L.orc_wm_build(_ptr(Pp), d, m, B, Bp, bitshift)
+        ps = PatternSet(P)
+        self.ps, self.d, self.m = ps, ps.d, ps.m
+        self.B, self.Bp, self.bitshift = B, Bp, bitshift
+        h = L.orc_wm_build_v(*ps.args(), B, Bp, bitshift)
         if not h:
-            raise ValueError(f"Wu-Manber needs m >= B and m >= B' (m={m}, B={B}, B'={Bp})")
+            raise ValueError(f"Wu-Manber needs every pattern at least B and B' long "
+                             f"(shortest {ps.shortest}, B={B}, B'={Bp})")
         type(self)._free = L.orc_wm_free
-        super().__init__(h, P)
+        super().__init__(h, ps)
 
     @property
     def tsize(self) -> int:
@@ -293,8 +336,9 @@ class WM(_Handle):
 def parallel_scan(obj, text, lo: int = 0, hi: int | None = None, workers: int | None = None,
                   parts: int | None = None):
     """Scan [lo, hi) as contiguous ranges on a thread pool (ctypes drops the
-    GIL) and concatenate in range order. Each range reads m-1 characters past
-    its end, as in the paper's split (Section 4.4)."""
+    GIL) and concatenate in range order. Each range reads up to (longest
+    pattern length - 1) characters past its end, as in the paper's split
+    (Section 4.4)."""
     T = _u8(text)
     n = len(T)
     hi = n if hi is None else min(hi, n)

@@ -318,3 +318,141 @@ def test_est_text_shape():
     assert 440 < lens.mean() < 560
     # same seed, same bytes
     assert np.array_equal(t, synth.est_text(1 << 20, seed=2))
+
+
+# ---------------------------------------------------------------------------
+# Pattern sets of different lengths (the Definition with a length per pattern)
+# ---------------------------------------------------------------------------
+
+def mixed_agree(T, P, wm_params=((3, 2, 2),)):
+    """bf, Win, AC and WM (for each usable (B, B', bitshift)) give one list."""
+    want = pairs(oracle.bf(T, P))
+    assert pairs(oracle.Win(P).scan(T)) == want
+    assert pairs(oracle.AC(P).scan(T)) == want
+    short = min(len(p) for p in P)
+    for B, Bp, bs in wm_params:
+        B, Bp = min(B, short), min(Bp, short)
+        assert pairs(oracle.WM(P, B=B, Bp=Bp, bitshift=bs).scan(T)) == want, (B, Bp, bs)
+    return want
+
+
+def rand_mixed(rng, alphabet=b"AC", n_max=40, d_max=6, len_max=5):
+    A = np.frombuffer(alphabet, np.uint8)
+    n = int(rng.integers(0, n_max + 1))
+    T = A[rng.integers(0, len(A), n)] if n else np.zeros(0, np.uint8)
+    d = int(rng.integers(1, d_max + 1))
+    P = [bytes(A[rng.integers(0, len(A), int(rng.integers(1, len_max + 1)))]) for _ in range(d)]
+    if d > 1 and rng.random() < 0.4:
+        P[-1] = P[0]                       # a duplicate
+    if d > 1 and rng.random() < 0.5 and len(P[0]) > 1:
+        P[1] = P[0][: int(rng.integers(1, len(P[0])))]   # a prefix of another
+    if d > 2 and rng.random() < 0.5 and len(P[0]) > 1:
+        P[2] = P[0][int(rng.integers(1, len(P[0]))):]    # a suffix of another
+    if n and rng.random() < 0.7:
+        L = len(P[0])
+        if n >= L:
+            s = int(rng.integers(0, n - L + 1))
+            P[0] = bytes(T[s:s + L])
+    return T.astype(np.uint8), P
+
+
+def test_mixed_hand_fixture():
+    with open(os.path.join(GOLDEN, "mixed_hand_example.json")) as f:
+        g = json.load(f)
+    for case in g["cases"]:
+        T = np.frombuffer(case["text"].encode(), np.uint8)
+        P = [p.encode() for p in case["patterns"]]
+        want = [tuple(x) for x in case["pairs"]]
+        assert mixed_agree(T, P, wm_params=((1, 1, 2), (2, 1, 1))) == want
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_mixed_bf_matches_regex_per_pattern(seed):
+    rng = np.random.default_rng(700 + seed)
+    T, P = rand_mixed(rng, alphabet=b"ACG", n_max=300, d_max=8, len_max=6)
+    Tb = bytes(T)
+    want = []
+    for r, p in enumerate(P):
+        want += [(mt.start(), r) for mt in re.finditer(b"(?=" + re.escape(p) + b")", Tb)]
+    assert pairs(oracle.bf(T, P)) == sorted(want)
+
+
+def test_mixed_exhaustive_tiny():
+    sets = [[b"A", b"AA", b"AAA"], [b"AC", b"C", b"CAC", b"C"], [b"CA", b"ACA", b"A", b"CCA"],
+            [b"AAC", b"A", b"AACA", b"AC"]]
+    for P in sets:
+        for n in range(0, 8):
+            for t in itertools.product(b"AC", repeat=n):
+                mixed_agree(np.array(t, np.uint8), P, wm_params=((3, 2, 2), (1, 1, 1), (2, 2, 8)))
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_mixed_random_agreement(seed):
+    rng = np.random.default_rng(800 + seed)
+    T, P = rand_mixed(rng, alphabet=b"ACGTN\n" if seed % 3 == 0 else b"ACGT", n_max=400,
+                      d_max=12, len_max=9)
+    mixed_agree(T, P, wm_params=((3, 2, 2), (2, 1, 2), (1, 1, 0)))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_ac_merged_output_is_every_pattern_suffix(seed):
+    """The merged output set of a state holds exactly the patterns that are
+    suffixes of the state's label (Section 3.1: a state reports a pattern
+    when it ends there; with several lengths a pattern can end inside a
+    longer path)."""
+    rng = np.random.default_rng(900 + seed)
+    _, P = rand_mixed(rng, alphabet=b"ACG", n_max=0, d_max=10, len_max=6)
+    ac = oracle.AC(P)
+    labels = state_labels(ac)
+    assert len(labels) == ac.nstates
+    for q, lab in labels.items():
+        want = [r for r, p in enumerate(P) if lab.endswith(p)]
+        assert ac.output_all(q) == want, (lab, want)
+        assert ac.output(q) == [r for r, p in enumerate(P) if lab == p]
+
+
+def test_mixed_wm_shift_uses_the_shortest_length():
+    """SHIFT over blocks of every pattern's first w characters, w the
+    shortest length (Section 3.2 with m read as the shortest length); HASH
+    keyed on the block ending those w characters."""
+    rng = np.random.default_rng(31)
+    A = np.frombuffer(b"ACGT", np.uint8)
+    P = [bytes(A[rng.integers(0, 4, int(L))]) for L in rng.integers(4, 10, 25)]
+    B, Bp, bs = 3, 2, 2
+    wm = oracle.WM(P, B=B, Bp=Bp, bitshift=bs)
+    w = min(len(p) for p in P)
+    best = {}
+    for p in P:
+        for q in range(B, w + 1):
+            h = shift_add(p[q - B:q], bs)
+            best[h] = min(best.get(h, w - B + 1), w - q)
+    table = wm.shift_table()
+    for h in range(wm.tsize):
+        assert table[h] == best.get(h, w - B + 1), h
+    for h in {shift_add(p[w - B:w], bs) for p in P}:
+        assert wm.hash_list(h) == [r for r, p in enumerate(P) if shift_add(p[w - B:w], bs) == h]
+
+
+def test_equal_lengths_as_list_equal_array_form():
+    text, ps = synth.workload_small()
+    T = text[:50000]
+    P = ps.patterns
+    as_list = [bytes(p) for p in P]
+    for cls in (oracle.Win, oracle.AC, oracle.WM):
+        a, b = cls(P).scan(T), cls(as_list).scan(T)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("parts", [1, 3, 17])
+def test_mixed_split_concatenation_equals_whole(parts):
+    """Contiguous ranges of starting positions, each reading up to (longest
+    length - 1) characters past its end (Section 4.4's split), concatenate to
+    the whole list."""
+    rng = np.random.default_rng(41)
+    T = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, 20000)]
+    P = [bytes(T[s:s + L]) for s, L in zip(rng.integers(0, 19000, 30), rng.integers(2, 12, 30))]
+    P += [p[:3] for p in P[:5]] + [p[-2:] for p in P[5:10]]
+    whole = oracle.bf(T, P)
+    for obj in (oracle.Win(P), oracle.AC(P), oracle.WM(P, B=2, Bp=2)):
+        got = oracle.parallel_scan(obj, T, parts=parts, workers=4)
+        assert np.array_equal(got[0], whole[0]) and np.array_equal(got[1], whole[1])
