@@ -79,6 +79,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden")
+
+
+def golden(name: str):
+    """Expected values of a full-size workload written from the CPU oracle
+    alone (tests/golden/make_digests.py), or None when absent."""
+    try:
+        with open(os.path.join(GOLDEN_DIR, f"{name}_digests.json")) as f:
+            return json.load(f)
+    except OSError:
+        return None
+
+
+def listdigest():
+    """The order-sensitive list digest the expected values use."""
+    if GOLDEN_DIR not in sys.path:
+        sys.path.insert(0, GOLDEN_DIR)
+    import listdigest as ld
+    return ld
+
+
 def workload(name: str):
     import synth
     if name == "est256":
@@ -173,6 +194,11 @@ def run_sweep(args):
     log("[bench] generating 1 GiB EST-shaped text")
     text = synth.workload_sweep_text()
     n = len(text)
+    gold = golden("sweep")
+    if gold is not None:
+        import hashlib
+        if hashlib.sha256(text.tobytes()).hexdigest() != gold["text_sha256"]:
+            gold = None  # the generator changed: no expected values for this text
     dev = torch.from_numpy(text).cuda()
     stream = torch.cuda.current_stream()
     rows = []
@@ -207,6 +233,17 @@ def run_sweep(args):
                 counts = cbuf.to(torch.int64) & 0xFFFFFFFF
                 if int(counts.sum()) != M:
                     raise SystemExit(f"per-pattern counts do not sum to the list length at d={d} m={m}")
+                parity = None
+                if gold is not None:
+                    import hashlib
+                    g = next(r for r in gold["sets"] if r["d"] == d and r["m"] == m)
+                    dig = f"{listdigest().digest_torch(sc.out[:M]):016x}"
+                    csha = hashlib.sha256(cbuf.cpu().numpy().view(np.uint32).astype("<u4")
+                                          .tobytes()).hexdigest()
+                    parity = bool(M == g["total"] and dig == g["digest"] and csha == g["counts_sha256"])
+                    if not parity:
+                        raise SystemExit(f"d={d} m={m} {algo}: list differs from the oracle's "
+                                         f"({M} vs {g['total']} pairs)")
                 alg_bytes = n + 8 * M + info["table_bytes"]
                 rows.append({
                     "d": d, "m": m, "algo": algo, "gbps": round(n / (kms * 1e-3) / 1e9, 2),
@@ -218,6 +255,7 @@ def run_sweep(args):
                     "placement": "lds" if info["table_bytes"] + 1024 <= 160 * 1024 else "hot",
                     "patterns_hit": int((counts > 0).sum()), "max_count": int(counts.max()),
                     "count_ms": round(count_ms, 4),
+                    "equals_oracle": parity,
                     "build_s": round(build_s, 3)})
                 log(f"[bench] d={d} m={m} {algo}: {rows[-1]['gbps']} GB/s, {M} matches")
                 del sc, count, ix
@@ -379,7 +417,25 @@ def run_batched(args):
     log(f"[bench] db {t_db:.1f}s, fit {t_fit:.1f}s, default variant {tune.VARIANTS[kdef]}")
     log(f"[bench] batch: {args.batch_texts} texts")
     b = synth.workload_batch(n_texts=args.batch_texts, n_sets=64, seed=20)
-    res = selection.evaluate(b, tuner, sel, kdef, log=log)
+    gold = golden("batch") if args.batch_texts == 4096 else None
+    parity = {}
+
+    def check(name, bs):
+        """Every text's list of this policy's last replay against the
+        oracle's (pair count and order-sensitive digest)."""
+        if gold is None:
+            return
+        tot = bs.totals_host()
+        ok = bool(np.array_equal(tot, np.array(gold["counts"], np.int64)))
+        if ok:
+            dg = listdigest().segment_digests_torch(
+                bs.out, torch.from_numpy(bs.out_offs[:-1].astype(np.int64)).cuda(),
+                torch.from_numpy(tot.astype(np.int64)).cuda())
+            ok = dg == [int(x, 16) for x in gold["digests"]]
+        parity[name] = ok
+        log(f"[bench] batch policy {name}: lists {'equal' if ok else 'DIFFER FROM'} the oracle's")
+
+    res = selection.evaluate(b, tuner, sel, kdef, log=log, check=check)
     res.pop("_state")
     line = {"metric": METRIC, "workload": "batch",
             "value": round(res["learned_gbps"], 2), "unit": "GB/s",
@@ -394,6 +450,7 @@ def run_batched(args):
             "regret": round(res["regret"], 4), "fallback_rate": round(res["fallback_rate"], 4),
             "gain_over_default": round(res["gain_over_default"], 4),
             "totals_agree": res["totals_agree"], "matches": res["matches"],
+            "equals_oracle": parity or None,
             "text_bytes": res["text_bytes"], "launches": {k: res[f"{k}_launches"] for k in
                                                           ("exhaustive", "learned", "default")},
             "pick_agreement": round(res["pick_agreement"], 4),

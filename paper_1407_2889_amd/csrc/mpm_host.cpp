@@ -672,19 +672,46 @@ static mpm_status check_counts(const mpm_index *ix, uint64_t ns, uint32_t lane_b
 
 extern "C" {
 
+}  // extern "C"
+
+namespace mpm {
+// Workspace of a single-text scan: the header and one status word per chunk
+// (the minimum), then the staging area, which holds every occurrence a lane
+// can have (one distinct string per starting position) when the workspace
+// has room for it (the full size); a smaller staging area only means that
+// lanes with more occurrences than it holds walk their range again.
+mpm_status workspace_sizes(const mpm_index *idx, uint64_t n, const mpm_variant *v,
+                           uint64_t *min_bytes, uint64_t *full_bytes, const char *who)
+{
+    if (!idx)
+        return fail(MPM_EINVAL, "%s: null index", who);
+    LaunchCfg cfg;
+    mpm_status st = resolve_variant(idx, v, 0, &cfg);
+    if (st)
+        return st;
+    const uint64_t tb = tile_bytes(cfg);
+    const uint64_t nt = (n_starts(n, idx->m) + tb - 1) / tb;
+    *min_bytes = WS_HEADER_BYTES + 8 * nt;
+    *full_bytes = *min_bytes;
+    if (full_bytes != min_bytes && nt) {
+        st = resolve_variant(idx, v, nt, &cfg);
+        if (st)
+            return st;
+        *full_bytes = align_up(*min_bytes, 256) + (uint64_t)cfg.grid * tb * sizeof(mpm_match);
+    }
+    return MPM_OK;
+}
+}  // namespace mpm
+
+extern "C" {
+
 mpm_status mpm_workspace_bytes(const mpm_index *idx, uint64_t n, const mpm_variant *v,
                                uint64_t *bytes)
 {
     if (!idx || !bytes)
         return fail(MPM_EINVAL, "mpm_workspace_bytes: null argument");
-    LaunchCfg cfg;
-    mpm_status st = resolve_variant(idx, v, 0, &cfg);
-    if (st)
-        return st;
-    uint64_t tb = tile_bytes(cfg);
-    uint64_t nt = (n_starts(n, idx->m) + tb - 1) / tb;
-    *bytes = WS_HEADER_BYTES + 8 * nt;
-    return MPM_OK;
+    uint64_t lo = 0;
+    return workspace_sizes(idx, n, v, &lo, bytes, "mpm_workspace_bytes");
 }
 
 }  // extern "C"
@@ -729,6 +756,17 @@ mpm_status scan_with_workspace(const mpm_index *idx, const uint8_t *d_text, uint
         return st;
     ScanDev sd;
     memset(&sd, 0, sizeof sd);
+    // staging: as many slots per virtual lane as the workspace holds, at most
+    // one per starting position of the lane
+    const uint64_t stage_off = align_up(WS_HEADER_BYTES + 8 * nt, 256);
+    if (work_bytes > stage_off) {
+        const uint64_t per_slot = (uint64_t)cfg.grid * cfg.block_threads * cfg.ilp * sizeof(mpm_match);
+        const uint64_t slots = std::min<uint64_t>(cfg.lane_bytes, (work_bytes - stage_off) / per_slot);
+        if (slots) {
+            sd.stage = (mpm_match *)((uint8_t *)d_work + stage_off);
+            sd.stage_cap = (uint32_t)slots;
+        }
+    }
     if (cfg.csr_lds) {
         sd.csr_uoff_words = csr_uoff_words(idx);
         sd.csr_uids_words = csr_uids_words(idx);
@@ -805,7 +843,7 @@ struct mpm_batch {
         std::vector<BatchText> texts;
         std::vector<BatchIndex> idx;
         uint64_t ntiles = 0;
-        uint64_t text_off = 0, idx_off = 0, work_off = 0;
+        uint64_t text_off = 0, idx_off = 0, work_off = 0, stage_off = 0;
     };
     std::vector<mpm_request> reqs;
     std::vector<Group> groups;
@@ -958,6 +996,8 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             off = align_up(off + g.idx.size() * sizeof(BatchIndex), 256);
             g.work_off = off;
             off = align_up(off + WS_HEADER_BYTES + 8 * g.ntiles, 256);
+            g.stage_off = off;
+            off = align_up(off + (uint64_t)g.grid * g.W * BATCH_STAGE_CAP * sizeof(mpm_match), 256);
         }
         b->zero_off = off;
         off = align_up(off + 8 * b->zero_totals.size() + 8, 256);
@@ -1050,6 +1090,8 @@ mpm_status mpm_batch_run(const mpm_batch *cb, void *stream)
         bd.ntiles = g.ntiles;
         bd.hdr = (uint32_t *)(b->d_buf + g.work_off);
         bd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
+        bd.stage = (mpm_match *)(b->d_buf + g.stage_off);
+        bd.stage_cap = BATCH_STAGE_CAP;
         mpm_status st = launch_batch(bd, g.kind, g.W, g.grid, g.lds, ls);
         if (st)
             return st;
@@ -1113,7 +1155,8 @@ mpm_status mpm_batch_replay(const mpm_batch *b, void *stream)
 // ---------------------------------------------------------------------------
 static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
                               const mpm_variant *v, LaunchCfg *cfg, uint64_t *nt_copy,
-                              uint64_t *idx_off, uint64_t *work_off, uint64_t *bytes)
+                              uint64_t *idx_off, uint64_t *work_off, uint64_t *stage_off,
+                              uint32_t *grid, uint64_t *bytes)
 {
     if (!idx || copies == 0)
         return fail(MPM_EINVAL, "mpm_tune: null index or zero copies");
@@ -1128,7 +1171,12 @@ static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
     *nt_copy = (n_starts(n, idx->m) + tb - 1) / tb;
     *idx_off = align_up((uint64_t)copies * sizeof(BatchText), 256);
     *work_off = align_up(*idx_off + sizeof(BatchIndex), 256);
-    *bytes = *work_off + WS_HEADER_BYTES + 8 * (*nt_copy) * copies;
+    *stage_off = align_up(*work_off + WS_HEADER_BYTES + 8 * (*nt_copy) * copies, 256);
+    *grid = *nt_copy ? batch_grid(batch_kind(idx, *cfg), cfg->block_threads, cfg->lds_bytes,
+                                  *nt_copy * copies, v ? v->grid : 0)
+                     : 1;
+    *bytes = *stage_off + (uint64_t)(*grid) * cfg->block_threads * BATCH_STAGE_CAP *
+                              sizeof(mpm_match);
     return MPM_OK;
 }
 
@@ -1136,8 +1184,9 @@ uint64_t mpm_tune_work_bytes(const mpm_index *idx, uint64_t n, uint32_t copies,
                              const mpm_variant *v)
 {
     LaunchCfg cfg;
-    uint64_t nt, io, wo, bytes;
-    if (tune_layout(idx, n, copies, v, &cfg, &nt, &io, &wo, &bytes))
+    uint64_t nt, io, wo, so, bytes;
+    uint32_t grid;
+    if (tune_layout(idx, n, copies, v, &cfg, &nt, &io, &wo, &so, &grid, &bytes))
         return 0;
     return bytes;
 }
@@ -1156,8 +1205,9 @@ mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n
     if (((uintptr_t)d_work) & 255)
         return fail(MPM_EINVAL, "mpm_tune_time: workspace must be 256-byte aligned");
     LaunchCfg cfg;
-    uint64_t nt, io, wo, bytes;
-    mpm_status st = tune_layout(idx, n, copies, v, &cfg, &nt, &io, &wo, &bytes);
+    uint64_t nt, io, wo, so, bytes;
+    uint32_t grid;
+    mpm_status st = tune_layout(idx, n, copies, v, &cfg, &nt, &io, &wo, &so, &grid, &bytes);
     if (st)
         return st;
     if (work_bytes < bytes)
@@ -1198,9 +1248,9 @@ mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n
         bd.ntiles = ntiles;
         bd.hdr = (uint32_t *)((uint8_t *)d_work + wo);
         bd.status = (uint64_t *)((uint8_t *)d_work + wo + WS_HEADER_BYTES);
+        bd.stage = (mpm_match *)((uint8_t *)d_work + so);
+        bd.stage_cap = BATCH_STAGE_CAP;
         const uint32_t kind = batch_kind(idx, cfg);
-        const uint32_t grid = batch_grid(kind, cfg.block_threads, cfg.lds_bytes, ntiles,
-                                         v ? v->grid : 0);
         hipEvent_t a, z;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&z) != hipSuccess)
             return fail(MPM_EHIP, "mpm_tune_time: event creation failed");

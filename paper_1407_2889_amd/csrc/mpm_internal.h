@@ -89,7 +89,11 @@ struct TextDesc {
 
 // Workspace header words (uint32): ticket counter, finished-workgroup
 // counter, launch epoch, device error flag. Followed (at byte 64) by one
-// uint64 look-back status word per tile.
+// uint64 look-back status word per tile, then (256-byte aligned) by the
+// staging area: per workgroup, `stage_cap` slots for each of its virtual
+// lanes, slot j of virtual lane v at (j * lanes + v), one (position, string)
+// pair each. A lane keeps its first occurrences in registers, stages the next
+// stage_cap ones there, and walks its range again only past those.
 enum { WS_TICKET = 0, WS_DONE = 1, WS_EPOCH = 2, WS_ERR = 3 };
 // Device error flag bits.
 enum { WS_ERR_LOOKBACK = 1u, WS_ERR_LDS_LAYOUT = 2u };
@@ -107,6 +111,9 @@ struct ScanDev {
     // (0: read from global memory), with its word counts.
     uint32_t csr_uoff_lds, csr_uids_lds;
     uint32_t csr_uoff_words, csr_uids_words;
+    mpm_match *stage;     // staging area (null when stage_cap is 0)
+    uint32_t stage_cap;   // staged occurrences per virtual lane
+    uint32_t pad;
 };
 
 // Batched launches: one descriptor per text (in queue order) and one per
@@ -146,7 +153,15 @@ struct BatchDev {
     uint64_t ntiles;
     uint32_t *hdr;
     uint64_t *status;
+    mpm_match *stage;     // staging area (null when stage_cap is 0)
+    uint32_t stage_cap;   // staged occurrences per lane
+    uint32_t pad2;
 };
+
+// Staged occurrences per lane: single-text scans stage a lane's whole range
+// when the workspace allows; batched launches (many workspaces at once)
+// stage at most this many.
+static const uint32_t BATCH_STAGE_CAP = 16;
 
 // Look-back status word: [63:38] epoch, [37:36] flag, [35:0] value.
 static const uint64_t ST_VAL_BITS = 36;

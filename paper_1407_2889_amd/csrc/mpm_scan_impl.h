@@ -284,7 +284,7 @@ __device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_
                                           uint32_t u, const IdMap &im)
 {
     GLB_AS v2u *out = (GLB_AS v2u *)out_;
-    if (im.dupfree) {
+    if (u < im.n_single) {  // one id, at CSR slot u (single-id strings come first)
         if (ob < cap)
             out[ob] = v2u{pos, im.id(u)};
         ++ob;
@@ -1208,16 +1208,26 @@ struct WmWalk {
 // ---------------------------------------------------------------------------
 // One chunk (phases A-C). The chunk is chunk g of its text; base is its
 // first starting position, `starts` how many starting positions it holds.
+// Staging area of one workgroup: slot j of virtual lane v at j * lanes + v
+// (slots of neighbouring lanes are neighbours, so lanes that stage or read
+// their j-th occurrence together touch one contiguous run).
+struct Stage {
+    GLB_AS v2u *base;  // this workgroup's area (null: no staging)
+    uint32_t cap;      // slots per virtual lane
+    uint32_t lanes;    // virtual lanes of the workgroup
+};
+
 template <class Walk, int W>
 __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> text, uint64_t n,
                                               mpm_match *out, uint64_t cap, uint64_t *total,
                                               uint64_t first_g, uint64_t nt, uint64_t g,
                                               uint32_t L, uint32_t m, uint32_t epoch,
                                               const IdMap &im, uint32_t *hdr, uint64_t *status,
-                                              uint64_t *s_scan)
+                                              uint64_t *s_scan, const Stage &stg)
 {
     constexpr int I = Walk::ILP;
     constexpr int KS = I == 1 ? K_SLOTS : 2;  // occurrences kept per virtual lane
+    const uint32_t scap = stg.base ? stg.cap : 0u;
     const uint64_t chunk = (uint64_t)W * L * I;
     const uint64_t lt = g - first_g;
     const uint64_t ns = n - m + 1;
@@ -1233,44 +1243,44 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
         hi[v] = (l0 + L) < starts ? (l0 + L) : (uint32_t)starts;
     }
 
-    // Phase A: count and keep the first occurrences.
-    uint32_t nu[I], nid[I];
+    // Phase A: count, keep the first occurrences in registers, stage the
+    // next ones in the workspace; lastp[v] is the start of the last one kept
+    // or staged.
+    uint32_t nu[I], nid[I], lastp[I];
     uint32_t so[I][KS], su[I][KS];
 #pragma unroll
     for (int v = 0; v < I; ++v) {
         nu[v] = 0;
         nid[v] = 0;
+        lastp[v] = 0;
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             so[v][k] = 0;
             su[v][k] = 0;
         }
     }
-    auto rec0 = [&](uint64_t start, uint32_t u) {
-        if (nu[0] < (uint32_t)KS) {
+    auto rec = [&](int v, uint64_t start, uint32_t u) {
+        if (nu[v] < (uint32_t)KS) {
 #pragma unroll
             for (int k = 0; k < KS; ++k)
-                if (nu[0] == (uint32_t)k) {
-                    so[0][k] = (uint32_t)start;
-                    su[0][k] = u;
+                if (nu[v] == (uint32_t)k) {
+                    so[v][k] = (uint32_t)start;
+                    su[v][k] = u;
                 }
+            lastp[v] = (uint32_t)start;
+        } else if (nu[v] - (uint32_t)KS < scap) {
+            stg.base[(uint64_t)(nu[v] - KS) * stg.lanes + threadIdx.x + v * W] =
+                v2u{(uint32_t)start, u};
+            lastp[v] = (uint32_t)start;
         }
-        ++nu[0];
-        nid[0] += im.count(u);
+        ++nu[v];
+        nid[v] += im.count(u);
     };
+    auto rec0 = [&](uint64_t start, uint32_t u) { rec(0, start, u); };
     if constexpr (I == 1) {
         wk.lane(text, n, base, lo[0], hi[0], rec0);
     } else {
-        auto rec1 = [&](uint64_t start, uint32_t u) {
-#pragma unroll
-            for (int k = 0; k < KS; ++k)
-                if (nu[I - 1] == (uint32_t)k) {
-                    so[I - 1][k] = (uint32_t)start;
-                    su[I - 1][k] = u;
-                }
-            ++nu[I - 1];
-            nid[I - 1] += im.count(u);
-        };
+        auto rec1 = [&](uint64_t start, uint32_t u) { rec(I - 1, start, u); };
         wk.lane2(text, n, base, lo[0], hi[0], lo[I - 1], hi[I - 1], rec0, rec1);
     }
 
@@ -1292,9 +1302,17 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
             if ((uint32_t)k < nu[v])
                 write_ids(out, cap, o, so[v][k], su[v][k], im);
         if (nu[v] > (uint32_t)KS) {
-            // The rest start after the last kept one (one distinct string per
-            // start): walk again from there, from the root / an empty window.
-            const uint32_t lo2 = (uint32_t)((uint64_t)so[v][KS - 1] + 1 - base);
+            const uint32_t ns_ = min(nu[v] - (uint32_t)KS, scap);
+            for (uint32_t j = 0; j < ns_ && o < cap; ++j) {
+                const v2u e = stg.base[(uint64_t)j * stg.lanes + threadIdx.x + v * W];
+                write_ids(out, cap, o, e.x, e.y, im);
+            }
+        }
+        if (nu[v] > (uint32_t)KS + scap && o < cap) {
+            // The rest start after the last kept or staged one (one distinct
+            // string per start): walk again from there, from the root / an
+            // empty window.
+            const uint32_t lo2 = (uint32_t)((uint64_t)lastp[v] + 1 - base);
             wk.lane_again(text, n, base, lo2, hi[v], [&](uint64_t start, uint32_t u) {
                 write_ids(out, cap, o, (uint32_t)start, u, im);
             });
@@ -1359,6 +1377,12 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
         copy_to_lds<W>(im.lds_uids, (const uint8_t *)uids_, 4 * sd.csr_uids_words);
     }
 
+    Stage stg;
+    stg.cap = sd.stage_cap;
+    stg.lanes = Walk::ILP * W;
+    stg.base = sd.stage ? (GLB_AS v2u *)sd.stage + (uint64_t)blockIdx.x * stg.cap * stg.lanes
+                        : nullptr;
+
     Walk wk;
     wk.template setup<W>(a, unused);
     if (threadIdx.x == 0)
@@ -1390,7 +1414,7 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
             break;
         process_chunk<Walk, W>(wk, (glb_cptr<uint8_t>)s_td.text, s_td.n, s_td.out, s_td.cap,
                                s_td.total, s_td.tile_begin, s_td.ntiles, g, L, m, s_epoch, im,
-                               hdr, status, s_scan);
+                               hdr, status, s_scan, stg);
         __syncthreads();
     }
     finish_launch(hdr, s_epoch);
@@ -1407,7 +1431,7 @@ __device__ __forceinline__ void batch_chunk(const Dev &dev, glb_cptr<uint8_t> te
                                             uint64_t n, mpm_match *out, uint64_t cap,
                                             uint64_t *total, uint64_t first_g, uint64_t nt,
                                             uint64_t g, uint32_t L, uint32_t epoch, uint32_t *hdr,
-                                            uint64_t *status, uint64_t *s_scan)
+                                            uint64_t *status, uint64_t *s_scan, const Stage &stg)
 {
     Walk wk;
     wk.bind(dev);
@@ -1419,7 +1443,7 @@ __device__ __forceinline__ void batch_chunk(const Dev &dev, glb_cptr<uint8_t> te
     im.dupfree = dev.dupfree;
     im.n_single = dev.n_single;
     process_chunk<Walk, W>(wk, text, n, out, cap, total, first_g, nt, g, L, dev.m, epoch, im,
-                           hdr, status, s_scan);
+                           hdr, status, s_scan, stg);
 }
 
 template <class Walk>
@@ -1451,6 +1475,11 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
     uint32_t *const hdr = bd.hdr;
     uint64_t *const status = bd.status;
     const BatchText *const texts = bd.texts;
+    Stage stg;
+    stg.cap = bd.stage_cap;
+    stg.lanes = W;
+    stg.base = bd.stage ? (GLB_AS v2u *)bd.stage + (uint64_t)blockIdx.x * stg.cap * stg.lanes
+                        : nullptr;
     if (threadIdx.x == 0)
         s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t loaded = 0xffffffffu;  // index whose tables LDS holds (uniform)
@@ -1484,7 +1513,7 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
         }
         batch_chunk<Walk, W>(dev, (glb_cptr<uint8_t>)s_bt.td.text, s_bt.td.n, s_bt.td.out,
                              s_bt.td.cap, s_bt.td.total, s_bt.td.tile_begin, s_bt.td.ntiles, g,
-                             s_bt.lane_bytes, s_epoch, hdr, status, s_scan);
+                             s_bt.lane_bytes, s_epoch, hdr, status, s_scan, stg);
         __syncthreads();
     }
     finish_launch(hdr, s_epoch);

@@ -62,10 +62,12 @@ def uniform_choice(k: int, valid_row: np.ndarray) -> int:
     return tune.VARIANTS.index((a, L, W, tune.PLACEMENTS[1]))
 
 
-def run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps: int = 5):
+def run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps: int = 5, check=None):
     """Capture the batch with request i under variant choice[i] and return
     (median replay ms, totals, launch count). ms_known [R, 24] (or None)
-    gives the per-request times the queue order is built from."""
+    gives the per-request times the queue order is built from. check(bs),
+    if given, is called with the BatchScan after the timed replays (its
+    outputs then hold the last replay's lists)."""
     import torch
     R = len(pset)
     idx = [pset[i].index(int(choice[i])) for i in range(R)]
@@ -86,11 +88,13 @@ def run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps: int = 5):
         z.record()
     torch.cuda.synchronize()
     tms = float(np.median([a.elapsed_time(z) for a, z in ev]))
+    if check is not None:
+        check(bs)
     return tms, bs.totals_host(), bs.groups
 
 
 def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
-             margin: float = 0.05, reps: int = 5, log=None):
+             margin: float = 0.05, reps: int = 5, log=None, check=None):
     """Run the three policies on batch b (texts, pattern sets and the set of
     each text: ``b.texts``, ``b.sets[k].patterns``, ``b.pairing``); returns a
     result dict."""
@@ -134,15 +138,16 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
     # default: none.
     ms_learned = np.where(fallback[:, None], ms, ms_pred)
 
-    def run(choice, ms_known):
-        return run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps)
+    def run(choice, ms_known, name):
+        return run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps,
+                         check=(lambda bs: check(name, bs)) if check else None)
 
     total_bytes = int(np.sum(lens))
     res = {"requests": R, "text_bytes": total_bytes}
     totals = {}
     for name, choice, known in (("exhaustive", exh, ms), ("learned", final, ms_learned),
                                 ("default", default, None)):
-        tms, tot, groups = run(choice, known)
+        tms, tot, groups = run(choice, known, name)
         res[f"{name}_ms"] = tms
         res[f"{name}_gbps"] = total_bytes / (tms * 1e-3) / 1e9
         res[f"{name}_launches"] = groups
