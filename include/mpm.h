@@ -200,6 +200,30 @@ mpm_status mpm_scan(const mpm_index *idx, const uint8_t *d_text, uint64_t n,
                     mpm_match *d_out, uint64_t capacity, void *d_work, uint64_t work_bytes,
                     uint64_t *d_total, const mpm_variant *v, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): mpm_scan
+ * without a caller workspace. The scan's workspace (counters, launch epoch and
+ * one look-back status word per chunk) lives in a static device array of
+ * MPM_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends; the first call on a device zero-fills it on
+ * `stream`, and every launch leaves its counters at zero for the next one.
+ * The call allocates nothing (no hipMalloc, no allocating library routine).
+ * The caller still passes the text, the output and the device total, with the
+ * meaning of mpm_scan; enqueued on `stream`, no wait.
+ * All calls on one device share its scratch: calls that overlap in time on one
+ * device (two streams, two threads) race and give wrong results; serialise
+ * them (one stream, or events).
+ * Errors: those of mpm_scan, and ENOMEM when the scan needs more than
+ * MPM_NOALLOC_SCRATCH_BYTES of workspace (mpm_workspace_bytes > the limit:
+ * more than (MPM_NOALLOC_SCRATCH_BYTES - 64) / 8 chunks of lane_bytes x
+ * block_threads starting positions), checked before anything is enqueued. A
+ * device-side look-back failure (never expected) is not reported here: use
+ * mpm_scan_sync for that check. */
+#define MPM_NOALLOC_SCRATCH_BYTES (1u << 20)
+mpm_status mpm_scan_noalloc(const mpm_index *idx, const uint8_t *d_text, uint64_t n,
+                            mpm_match *d_out, uint64_t capacity, uint64_t *d_total,
+                            const mpm_variant *v, void *stream);
+
 /* mpm_scan followed by a wait on `stream` and a read of the total into
  * *total (host). Returns EOVERFLOW when *total > capacity (the first
  * `capacity` pairs are valid), ESTATE when the device flagged a failure.

@@ -35,6 +35,7 @@ import torch  # noqa: E402,F401
 
 _L = C.CDLL(LIB_PATH)
 
+NOALLOC_SCRATCH_BYTES = 1 << 20  # MPM_NOALLOC_SCRATCH_BYTES
 MPM_OK, MPM_EINVAL, MPM_EOVERFLOW, MPM_ENOMEM, MPM_EHIP, MPM_ETOOBIG, MPM_EUNSUPPORTED, MPM_ESTATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 ALGO_AC, ALGO_WM = 1, 2
@@ -128,6 +129,7 @@ _sig("mpm_read_probe", C.c_int32, [_vp, _u64, _vp, _vp])
 _sig("mpm_count_ids", C.c_int32, [_vp, _u64, _u32, _vp, _vp])
 _sig("mpm_scan_host", C.c_int32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _u64, _vp, _u64, _vp,
                                   C.POINTER(Variant), _vp, C.POINTER(_u64)])
+_sig("mpm_scan_noalloc", C.c_int32, [_vp, _vp, _u64, _vp, _u64, _vp, C.POINTER(Variant), _vp])
 _sig("mpm_tune_time", C.c_int32, [_vp, _vp, _u64, _u32, C.POINTER(Variant), _vp, _u64, _vp, _vp,
                                   _u64, _u32, _vp, C.POINTER(C.c_float)])
 _sig("mpm_tune_work_bytes", _u64, [_vp, _u64, _u32, C.POINTER(Variant)])
@@ -147,7 +149,7 @@ EXPORTS = [
     "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
     "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
     "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam", "mpm_count_ids",
-    "mpm_scan_host",
+    "mpm_scan_host", "mpm_scan_noalloc",
 ]
 
 
