@@ -113,6 +113,19 @@ typedef struct {
  * one chain per lane; placement LDS (when goto rows and supply links fit) or
  * GLOBAL; single-text scans only (a batch plan refuses it). */
 #define MPM_VARIANT_SUPPLY 4u
+/* Dense output, for texts with many occurrences per position (short
+ * patterns against large sets): each lane owns 16 starting positions
+ * (lane_bytes is ignored) and marks, per position, the pattern string that
+ * starts there in an LDS array kept in position order; whole waves then write
+ * the pairs of 64 consecutive positions at a time to consecutive output
+ * slots, instead of every lane appending to its own output range (which,
+ * with many occurrences, leaves cache lines half written when they are
+ * evicted). Needs block_threads 1024; the marks take 64 KiB of LDS beside the
+ * tables (an Aho-Corasick hot part shrinks by as much; tables that then no
+ * longer fit are read through the caches). Single-text scans; a batch plan
+ * ignores the flag. EUNSUPPORTED with MPM_VARIANT_ILP2 or
+ * MPM_VARIANT_SUPPLY. */
+#define MPM_VARIANT_DENSE 8u
 
 /* Facts about a built index. */
 typedef struct {
@@ -288,6 +301,14 @@ typedef struct {
      * chunks take longest are queued first, so that long chunks do not end
      * up as the launch's tail. Does not affect results. */
     float cost_hint;
+    /* Device float[2] or NULL (autotuning; does not affect results). When
+     * set, every run of the batch adds to d_cost[0], for each chunk of this
+     * request, the wall-clock time a workgroup spent on it divided by the
+     * number of workgroups of its launch (the request's share of a launch
+     * that has the device to itself), and raises d_cost[1] to the longest
+     * such chunk time, both in microseconds (the caller zeroes them). A plan
+     * with such a request runs its launches one after another. */
+    float *d_cost;
 } mpm_request;
 
 typedef struct mpm_batch mpm_batch;
@@ -315,6 +336,13 @@ mpm_status mpm_batch_replay(const mpm_batch *b, void *stream);
 
 /* Number of group launches in the plan. */
 uint32_t mpm_batch_groups(const mpm_batch *b);
+
+/* The launch a request with this index and variant joins in a plan: two
+ * requests share a launch exactly when their keys are equal (walker kind,
+ * block size, LDS class). Lets a caller predict a plan's launches while it
+ * chooses variants; the value has no other meaning. Host-only.
+ * Errors: EINVAL, EUNSUPPORTED (as mpm_batch_plan). */
+mpm_status mpm_batch_launch_key(const mpm_index *idx, const mpm_variant *variant, uint32_t *key);
 
 void mpm_batch_free(mpm_batch *b);
 
@@ -400,9 +428,10 @@ mpm_status mpm_export_wm_shift(const mpm_index *idx, uint8_t *shift);
 
 /* Copy the unique-string index: uoff (d_unique + 1 entries) and ids (d
  * entries) so that ids[uoff[u] .. uoff[u+1]) are the ascending pattern ids of
- * distinct pattern string u. Distinct strings are numbered with those that
- * occur once in the pattern array first, then the repeated ones, each group
- * in ascending string order. Errors: EINVAL. */
+ * distinct pattern string u. Distinct strings are numbered by how many ids
+ * they stand for (those that occur once in the pattern array first, then
+ * those that occur twice, and so on), each group in ascending string order.
+ * Errors: EINVAL. */
 mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids);
 
 /* ---------------------------------------------------------------------- */

@@ -59,6 +59,7 @@ class Opts(C.Structure):
 VARIANT_NO_SWAR = 1
 VARIANT_ILP2 = 2
 VARIANT_SUPPLY = 4
+VARIANT_DENSE = 8
 
 
 class Variant(C.Structure):
@@ -88,7 +89,7 @@ class Info(C.Structure):
 class Request(C.Structure):
     _fields_ = [("idx", C.c_void_p), ("d_text", C.c_void_p), ("n", C.c_uint64),
                 ("d_out", C.c_void_p), ("capacity", C.c_uint64), ("d_total", C.c_void_p),
-                ("variant", Variant), ("cost_hint", C.c_float)]
+                ("variant", Variant), ("cost_hint", C.c_float), ("d_cost", C.c_void_p)]
 
 
 _vp, _u32, _u64 = C.c_void_p, C.c_uint32, C.c_uint64
@@ -122,6 +123,7 @@ _sig("mpm_batch_capture", C.c_int32, [_vp, _vp])
 _sig("mpm_batch_replay", C.c_int32, [_vp, _vp])
 _sig("mpm_batch_groups", _u32, [_vp])
 _sig("mpm_batch_free", None, [_vp])
+_sig("mpm_batch_launch_key", C.c_int32, [_vp, C.POINTER(Variant), C.POINTER(_u32)])
 _sig("mpm_export_ac", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_export_wm_shift", C.c_int32, [_vp, _vp])
 _sig("mpm_export_unique", C.c_int32, [_vp, _vp, _vp])
@@ -149,7 +151,7 @@ EXPORTS = [
     "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
     "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
     "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam", "mpm_count_ids",
-    "mpm_scan_host", "mpm_scan_noalloc",
+    "mpm_scan_host", "mpm_scan_noalloc", "mpm_batch_launch_key",
 ]
 
 
@@ -285,6 +287,15 @@ def workspace_bytes(ix: Index, n: int, var: Variant | None = None) -> int:
     out = C.c_uint64()
     _check(_L.mpm_workspace_bytes(ix.handle, n, C.byref(var) if var else None, C.byref(out)),
            "mpm_workspace_bytes")
+    return int(out.value)
+
+
+def launch_key(ix: Index, var: Variant | None = None) -> int:
+    """Key of the batched launch a request with this index and variant joins
+    (equal keys share a launch). Host-only."""
+    out = _u32()
+    _check(_L.mpm_batch_launch_key(ix.handle, C.byref(var) if var else None, C.byref(out)),
+           "mpm_batch_launch_key")
     return int(out.value)
 
 

@@ -42,7 +42,7 @@ class BatchScan:
     """
 
     def __init__(self, arena, offsets, lens, indexes, variants, capacities, device="cuda",
-                 cost_hints=None):
+                 cost_hints=None, timed: bool = False):
         torch = _torch()
         self.count = len(lens)
         self.lens = np.asarray(lens, np.int64)
@@ -52,6 +52,10 @@ class BatchScan:
         self.arena = arena
         self.out = torch.empty((max(1, int(self.out_offs[-1])), 2), dtype=torch.int32, device=device)
         self.totals = torch.zeros(max(1, self.count), dtype=torch.int64, device=device)
+        # timed: every run adds each request's share of its launch and raises
+        # its longest chunk time (us), costs[i] = (share, longest chunk)
+        self.costs = (torch.zeros((max(1, self.count), 2), dtype=torch.float32, device=device)
+                      if timed else None)
         self._indexes = list(indexes)
         reqs = (Request * max(1, self.count))()
         base_t, base_o, base_tot = arena.data_ptr(), self.out.data_ptr(), self.totals.data_ptr()
@@ -69,6 +73,7 @@ class BatchScan:
             v = variants[i]
             r.variant = Variant(v.lane_bytes, v.block_threads, v.placement, v.grid, v.flags)
             r.cost_hint = float(cost_hints[i]) if cost_hints is not None else 0.0
+            r.d_cost = self.costs.data_ptr() + 8 * i if timed else None
         h = C.c_void_p()
         _check(_L.mpm_batch_plan(reqs, self.count, C.byref(h)), "mpm_batch_plan")
         self._h = h

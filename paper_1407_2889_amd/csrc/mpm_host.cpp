@@ -75,17 +75,21 @@ static mpm_status dedup(const uint8_t *P, uint32_t d, uint32_t m, mpm_index *ix)
     ix->max_dup = std::max(ix->max_dup, run);
     ix->uoff.push_back(d);
     ix->du = (uint32_t)(ix->uoff.size() - 1);
-    // Number the distinct strings with a single id first, the repeated ones
-    // after them (each group in ascending string order): a reported string
-    // u < n_single then stands for exactly one id, and the scan needs the id
-    // lists only for the rest.
-    std::vector<uint32_t> single, multi;
-    for (uint32_t u = 0; u < ix->du; u++)
-        (ix->uoff[u + 1] - ix->uoff[u] == 1 ? single : multi).push_back(u);
-    ix->n_single = (uint32_t)single.size();
-    if (!multi.empty() && !single.empty()) {
-        std::vector<uint32_t> perm(single);
-        perm.insert(perm.end(), multi.begin(), multi.end());
+    // Number the distinct strings by their number of ids (ascending), each
+    // group in ascending string order: strings u < n_single stand for exactly
+    // one id, and within a group of strings with c ids the id list of u starts
+    // at group_off + (u - group_start) * c, so the scan counts and finds a
+    // string's ids without reading the CSR offsets.
+    std::vector<uint32_t> perm(ix->du);
+    std::iota(perm.begin(), perm.end(), 0u);
+    std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) {
+        return ix->uoff[a + 1] - ix->uoff[a] < ix->uoff[b + 1] - ix->uoff[b];
+    });
+    ix->n_single = 0;
+    while (ix->n_single < ix->du &&
+           ix->uoff[perm[ix->n_single] + 1] - ix->uoff[perm[ix->n_single]] == 1)
+        ix->n_single++;
+    if (ix->n_single < ix->du) {
         std::vector<uint32_t> uoff2(1, 0), uids2;
         std::vector<uint8_t> upats2;
         uids2.reserve(d);
@@ -100,6 +104,18 @@ static mpm_status dedup(const uint8_t *P, uint32_t d, uint32_t m, mpm_index *ix)
         ix->uoff.swap(uoff2);
         ix->uids.swap(uids2);
         ix->upats.swap(upats2);
+    }
+    // groups of strings sharing an id count above one
+    ix->grp_u0.clear();
+    ix->grp_cnt.clear();
+    ix->grp_off.clear();
+    for (uint32_t u = ix->n_single; u < ix->du; u++) {
+        const uint32_t c = ix->uoff[u + 1] - ix->uoff[u];
+        if (ix->grp_cnt.empty() || ix->grp_cnt.back() != c) {
+            ix->grp_u0.push_back(u);
+            ix->grp_cnt.push_back(c);
+            ix->grp_off.push_back(ix->uoff[u]);
+        }
     }
     return MPM_OK;
 }
@@ -693,7 +709,7 @@ mpm_status workspace_sizes(const mpm_index *idx, uint64_t n, const mpm_variant *
     const uint64_t nt = (n_starts(n, idx->m) + tb - 1) / tb;
     *min_bytes = WS_HEADER_BYTES + 8 * nt;
     *full_bytes = *min_bytes;
-    if (full_bytes != min_bytes && nt) {
+    if (full_bytes != min_bytes && nt && !cfg.dense) {  // dense output stages nothing
         st = resolve_variant(idx, v, nt, &cfg);
         if (st)
             return st;
@@ -758,8 +774,9 @@ mpm_status scan_with_workspace(const mpm_index *idx, const uint8_t *d_text, uint
     memset(&sd, 0, sizeof sd);
     // staging: as many slots per virtual lane as the workspace holds, at most
     // one per starting position of the lane
+    // (none for dense output, or for a counting call with no output at all)
     const uint64_t stage_off = align_up(WS_HEADER_BYTES + 8 * nt, 256);
-    if (work_bytes > stage_off) {
+    if (work_bytes > stage_off && capacity && !cfg.dense) {
         const uint64_t per_slot = (uint64_t)cfg.grid * cfg.block_threads * cfg.ilp * sizeof(mpm_match);
         const uint64_t slots = std::min<uint64_t>(cfg.lane_bytes, (work_bytes - stage_off) / per_slot);
         if (slots) {
@@ -780,6 +797,7 @@ mpm_status scan_with_workspace(const mpm_index *idx, const uint8_t *d_text, uint
     sd.ntiles = nt;
     sd.hdr = (uint32_t *)d_work;
     sd.status = (uint64_t *)((uint8_t *)d_work + WS_HEADER_BYTES);
+    sd.mark_lds = cfg.mark_lds;
     return launch_scan(idx, cfg, sd, stream);
 }
 }  // namespace mpm
@@ -831,6 +849,17 @@ mpm_status mpm_scan_sync(const mpm_index *idx, const uint8_t *d_text, uint64_t n
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
+// Launch key of a batch request: walker kind, block size and LDS class. Each
+// launch runs one kernel (one walker kind); its LDS size is the largest its
+// texts need, so texts with small tables are kept apart from texts whose
+// tables limit a CU to one or two workgroups.
+static uint32_t launch_key(uint32_t kind, const LaunchCfg &c)
+{
+    const uint32_t lds = c.lds_bytes;
+    const uint32_t lds_class = lds <= 8192 ? 0 : lds <= 32768 ? 1 : lds <= 65536 ? 2 : 3;
+    return (kind & 0xffu) << 16 | (c.block_threads & 0x3fffu) << 2 | lds_class;
+}
+
 struct mpm_batch {
     // One persistent launch per block size; its texts ordered by index and
     // walker kind so that LDS tables are reused across consecutive chunks.
@@ -851,6 +880,8 @@ struct mpm_batch {
     uint64_t zero_off = 0;
     uint64_t bytes = 0;
     uint8_t *d_buf = nullptr;
+    bool serial = false;       // launches one after another (timed requests)
+    float us_per_tick = 0.f;   // wall-clock tick length
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // Side streams (default priority) so that the plan's launches run as
@@ -878,14 +909,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             float hint;
             float group_hint;
         };
-        // Launch key: walker kind, block size and LDS class. Each launch runs
-        // one kernel (one walker kind); its LDS size is the largest its texts
-        // need, so texts with small tables are kept apart from texts whose
-        // tables limit a CU to one or two workgroups.
-        auto lds_class = [](uint32_t lds) -> uint32_t {
-            return lds <= 8192 ? 0 : lds <= 32768 ? 1 : lds <= 65536 ? 2 : 3;
-        };
-        std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<Item>> byw;
+        std::map<uint32_t, std::vector<Item>> byw;
         for (uint32_t k = 0; k < count; k++) {
             const mpm_request &r = reqs[k];
             if (!r.idx || !r.d_total || (r.n && !r.d_text) || (r.capacity && !r.d_out)) {
@@ -905,7 +929,8 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 continue;
             }
             mpm_variant v = r.variant;
-            v.flags &= ~MPM_VARIANT_ILP2;  // batched walkers run one range per lane
+            // batched walkers run one range per lane and write per lane
+            v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
             Item it;
             it.req = k;
             it.ix = r.idx;
@@ -925,7 +950,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return st;
             }
             it.kind = batch_kind(r.idx, it.cfg);
-            const auto key = std::make_tuple(it.kind, it.cfg.block_threads, lds_class(it.cfg.lds_bytes));
+            const uint32_t key = launch_key(it.kind, it.cfg);
             byw[key].push_back(it);
             if (r.variant.grid)
                 byw[key].back().cfg.grid = r.variant.grid;
@@ -951,8 +976,8 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 return x.hint > y.hint;
             });
             mpm_batch::Group g;
-            g.kind = std::get<0>(kv.first);
-            g.W = std::get<1>(kv.first);
+            g.kind = items.front().kind;
+            g.W = items.front().cfg.block_threads;
             std::map<const mpm_index *, uint32_t> slot;
             for (const Item &it : items) {
                 const mpm_request &r = reqs[it.req];
@@ -981,6 +1006,9 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 bt.index = si;
                 bt.kind = it.kind;
                 bt.lane_bytes = it.cfg.lane_bytes;
+                bt.cost = r.d_cost;
+                if (r.d_cost)
+                    b->serial = true;
                 g.texts.push_back(bt);
                 g.ntiles += nt;
                 g.lds = std::max(g.lds, it.cfg.lds_bytes);
@@ -1002,6 +1030,16 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
         b->zero_off = off;
         off = align_up(off + 8 * b->zero_totals.size() + 8, 256);
         b->bytes = off;
+        if (b->serial) {
+            int dev = 0, khz = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+                khz <= 0) {
+                delete b;
+                return fail(MPM_EHIP, "mpm_batch_plan: wall-clock rate unavailable");
+            }
+            b->us_per_tick = 1000.f / (float)khz;
+        }
         *out = b;
         g_err.clear();
         return MPM_OK;
@@ -1013,6 +1051,24 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
 uint64_t mpm_batch_device_bytes(const mpm_batch *b) { return b ? b->bytes : 0; }
 
 uint32_t mpm_batch_groups(const mpm_batch *b) { return b ? (uint32_t)b->groups.size() : 0; }
+
+mpm_status mpm_batch_launch_key(const mpm_index *idx, const mpm_variant *variant, uint32_t *key)
+{
+    if (!idx || !key)
+        return fail(MPM_EINVAL, "mpm_batch_launch_key: null argument");
+    mpm_variant v = variant ? *variant : mpm_variant{0, 0, 0, 0, 0};
+    v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
+    LaunchCfg cfg;
+    mpm_status st = resolve_variant(idx, &v, 0, &cfg);
+    if (st)
+        return st;
+    if (cfg.supply)
+        return fail(MPM_EUNSUPPORTED, "mpm_batch_launch_key: the supply-link walk runs in "
+                    "single-text scans only");
+    *key = launch_key(batch_kind(idx, cfg), cfg);
+    g_err.clear();
+    return MPM_OK;
+}
 
 mpm_status mpm_batch_upload(mpm_batch *b, void *d_buf, uint64_t bytes, void *stream)
 {
@@ -1070,7 +1126,7 @@ mpm_status mpm_batch_run(const mpm_batch *cb, void *stream)
         if (st)
             return st;
     }
-    const bool fan = b->groups.size() > 1;
+    const bool fan = b->groups.size() > 1 && !b->serial;
     hipStream_t main_s = (hipStream_t)stream;
     if (fan && hipEventRecord(b->fork, main_s) != hipSuccess)
         return fail(MPM_EHIP, "mpm_batch_run: fork event failed");
@@ -1092,6 +1148,7 @@ mpm_status mpm_batch_run(const mpm_batch *cb, void *stream)
         bd.status = (uint64_t *)(b->d_buf + g.work_off + WS_HEADER_BYTES);
         bd.stage = (mpm_match *)(b->d_buf + g.stage_off);
         bd.stage_cap = BATCH_STAGE_CAP;
+        bd.us_per_tick = b->us_per_tick;
         mpm_status st = launch_batch(bd, g.kind, g.W, g.grid, g.lds, ls);
         if (st)
             return st;
@@ -1161,7 +1218,7 @@ static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
     if (!idx || copies == 0)
         return fail(MPM_EINVAL, "mpm_tune: null index or zero copies");
     mpm_variant w = v ? *v : mpm_variant{0, 0, 0, 0, 0};
-    w.flags &= ~MPM_VARIANT_ILP2;
+    w.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
     mpm_status st = resolve_variant(idx, &w, 0, cfg);
     if (st)
         return st;
@@ -1229,6 +1286,7 @@ mpm_status mpm_tune_time(const mpm_index *idx, const uint8_t *d_text, uint64_t n
             bt[k].index = 0;
             bt[k].kind = batch_kind(idx, cfg);
             bt[k].lane_bytes = cfg.lane_bytes;
+            bt[k].cost = nullptr;
         }
         BatchIndex *bi = (BatchIndex *)(host.data() + io);
         if (idx->algo == MPM_ALGO_AC)

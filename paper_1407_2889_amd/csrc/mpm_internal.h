@@ -15,6 +15,23 @@ namespace mpm {
 // Kernel-argument descriptors (passed by value)
 // ---------------------------------------------------------------------------
 
+// Bytes at the start of a scan kernel's LDS before the matching tables: the
+// per-workgroup header (with the id groups below) and the byte-class map.
+static const uint32_t LDS_FIXED_BYTES = 1536;
+
+// Distinct strings numbered by their id count: strings below n_single have
+// one id (at CSR slot u); then groups k < n of strings sharing a count: group
+// k holds strings [u0[k], u0[k + 1]) with cnt[k] ids each, the first one's
+// ids from CSR slot off[k]. Strings from u0[n] on (past the groups kept
+// here) read the CSR offsets.
+static const int ID_GROUPS = 8;
+struct IdGroups {
+    uint32_t n;
+    uint32_t u0[ID_GROUPS + 1];
+    uint32_t cnt[ID_GROUPS];
+    uint32_t off[ID_GROUPS];
+};
+
 // Dense Aho-Corasick table. Row s holds `cp` entries: column 0 is the class of
 // bytes that occur in no pattern (always leads to the root), columns 1..cp-1
 // the pattern bytes in ascending order. States are numbered breadth-first, so
@@ -33,6 +50,7 @@ struct AcDev {
     uint32_t dfa_bytes;     // bytes of the table (multiple of 16)
     uint32_t dupfree;       // every distinct string has exactly one id
     uint32_t n_single;      // distinct strings below this have one id each
+    IdGroups grp;           // id count groups of the other strings
     uint32_t hot_states;    // hot placement: rows [0, hot_states) in LDS
     uint32_t hot_bytes;     // bytes of those rows (multiple of 16)
     // Goto rows (same numbering and columns as the table, all-ones for a
@@ -73,6 +91,7 @@ struct WmDev {
     uint32_t dupfree;
     uint32_t n_single;
     uint32_t shift_bytes;   // bytes of SHIFT at the start of `tables` (multiple of 16)
+    IdGroups grp;
 };
 
 // One text of a launch. Tiles of a launch are numbered globally; a text
@@ -113,7 +132,7 @@ struct ScanDev {
     uint32_t csr_uoff_words, csr_uids_words;
     mpm_match *stage;     // staging area (null when stage_cap is 0)
     uint32_t stage_cap;   // staged occurrences per virtual lane
-    uint32_t pad;
+    uint32_t mark_lds;    // dense output: LDS byte offset of the position marks
 };
 
 // Batched launches: one descriptor per text (in queue order) and one per
@@ -143,6 +162,7 @@ struct BatchText {
     uint32_t kind;        // BK_*
     uint32_t lane_bytes;
     uint32_t pad;
+    float *cost;          // per-request time share and longest chunk (null: not timed)
 };
 
 struct BatchDev {
@@ -155,7 +175,7 @@ struct BatchDev {
     uint64_t *status;
     mpm_match *stage;     // staging area (null when stage_cap is 0)
     uint32_t stage_cap;   // staged occurrences per lane
-    uint32_t pad2;
+    float us_per_tick;    // microseconds per wall-clock tick (timed requests)
 };
 
 // Staged occurrences per lane: single-text scans stage a lane's whole range
@@ -178,6 +198,10 @@ struct mpm_index {
     uint32_t m = 0, d = 0, du = 0, max_dup = 0;
     uint32_t n_single = 0;              // distinct strings 0..n_single-1 have one id each
     std::vector<uint32_t> uoff, uids;   // distinct strings -> ids
+    // Strings from n_single on come in groups sharing an id count: group k
+    // starts at string grp_u0[k], its strings have grp_cnt[k] ids each, and
+    // its first string's ids start at grp_off[k].
+    std::vector<uint32_t> grp_u0, grp_cnt, grp_off;
     std::vector<uint8_t> upats;         // du * m, ascending strings
 
     // Aho-Corasick
@@ -222,7 +246,11 @@ struct LaunchCfg {
     bool supply;          // AC: goto function and supply links at run time
     uint32_t ilp;         // virtual lanes per thread (1 or 2)
     uint32_t csr_lds;     // LDS byte offset of the id CSR (0: global memory)
+    bool dense;           // dense output (position marks in LDS)
+    uint32_t mark_lds;    // LDS byte offset of the marks (dense)
 };
+// LDS bytes of the dense output's position marks (1024 lanes x 16 positions).
+static const uint32_t DENSE_MARK_BYTES = 1024 * 16 * 4;
 // csr_in_lds: single-text scans may copy the id CSR to LDS (batched launches
 // keep it in global memory).
 mpm_status resolve_variant(const mpm_index *idx, const mpm_variant *v, uint64_t ntiles_hint,
@@ -236,7 +264,9 @@ mpm_status launch_scan(const mpm_index *idx, const LaunchCfg &cfg, const ScanDev
                        void *stream);
 mpm_status launch_zero_totals(uint64_t *const *d_totals_dev, uint32_t count, uint64_t *single,
                               void *stream);
-AcDev ac_dev(const mpm_index *ix);
+// reserve: LDS bytes the launch keeps beside the tables (the hot part of an
+// Aho-Corasick table shrinks by as much).
+AcDev ac_dev(const mpm_index *ix, uint32_t reserve = 0);
 WmDev wm_dev(const mpm_index *ix);
 uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c);
 // Batched launches run one kernel per walker kind (BK_*, with BK_SWAR).

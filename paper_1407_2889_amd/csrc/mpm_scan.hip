@@ -75,14 +75,28 @@ static DeviceLimits limits()
         if (L.cus <= 0)
             L.cus = 256;
         if (L.max_lds <= 0)
-            L.max_lds = 65536;
+            L.max_lds = 160 * 1024;  // gfx950's LDS per workgroup (host-only callers)
         cache[dev] = L;
         have[dev] = true;
     }
     return cache[dev];
 }
 
-AcDev ac_dev(const mpm_index *ix)
+static IdGroups id_groups(const mpm_index *ix)
+{
+    IdGroups g;
+    memset(&g, 0, sizeof g);
+    g.n = (uint32_t)std::min<size_t>(ix->grp_u0.size(), ID_GROUPS);
+    for (uint32_t k = 0; k < g.n; k++) {
+        g.u0[k] = ix->grp_u0[k];
+        g.cnt[k] = ix->grp_cnt[k];
+        g.off[k] = ix->grp_off[k];
+    }
+    g.u0[g.n] = g.n < ix->grp_u0.size() ? ix->grp_u0[g.n] : ix->du;
+    return g;
+}
+
+AcDev ac_dev(const mpm_index *ix, uint32_t reserve)
 {
     AcDev a;
     a.dfa = ix->d_image + ix->off_a;
@@ -96,6 +110,7 @@ AcDev ac_dev(const mpm_index *ix)
     a.dfa_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
     a.n_single = ix->n_single;
+    a.grp = id_groups(ix);
     a.swar_ok = ix->swar_ok;
     a.swar_shift = ix->swar_shift;
     uint32_t w[4];
@@ -109,7 +124,7 @@ AcDev ac_dev(const mpm_index *ix)
     a.perm_col_hi = w[3];
     // hot placement: as many whole rows as the LDS holds beside the fixed
     // regions (16-byte multiple)
-    const uint64_t budget = ((uint64_t)limits().max_lds - 1024u) & ~15ull;
+    const uint64_t budget = ((uint64_t)limits().max_lds - LDS_FIXED_BYTES - reserve) & ~15ull;
     const uint64_t hb = std::min<uint64_t>(budget, ix->table_bytes);
     a.hot_bytes = (uint32_t)hb;
     a.go = ix->keep_goto ? (const void *)(ix->d_image + ix->off_go) : nullptr;
@@ -136,6 +151,7 @@ WmDev wm_dev(const mpm_index *ix)
     a.table_bytes = (uint32_t)ix->table_bytes;
     a.dupfree = ix->max_dup == 1;
     a.n_single = ix->n_single;
+    a.grp = id_groups(ix);
     a.shift_bytes = (uint32_t)(((uint64_t)ix->shift16.size() * 2 + 15) / 16 * 16);
     return a;
 }
@@ -146,11 +162,11 @@ static bool has_hot(const mpm_index *ix)
     return ix->algo == MPM_ALGO_WM || ix->algo == MPM_ALGO_AC;
 }
 
-// LDS bytes of the hot part.
-static uint64_t hot_lds_bytes(const mpm_index *ix)
+// LDS bytes of the hot part (reserve: bytes the launch keeps beside it).
+static uint64_t hot_lds_bytes(const mpm_index *ix, uint32_t reserve)
 {
     if (ix->algo == MPM_ALGO_AC)
-        return ac_dev(ix).hot_bytes;
+        return ac_dev(ix, reserve).hot_bytes;
     return ((uint64_t)ix->shift16.size() * 2 + 15) / 16 * 16;
 }
 
@@ -190,8 +206,18 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
         return fail(MPM_EINVAL, "variant: block_threads=%u must be 256, 512 or 1024", W);
     if (d.placement > MPM_PLACE_HOT)
         return fail(MPM_EINVAL, "variant: unknown placement %u", d.placement);
-    if (d.flags & ~(MPM_VARIANT_NO_SWAR | MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY))
+    if (d.flags & ~(MPM_VARIANT_NO_SWAR | MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY | MPM_VARIANT_DENSE))
         return fail(MPM_EINVAL, "variant: unknown flags 0x%x", d.flags);
+    const bool dense = (d.flags & MPM_VARIANT_DENSE) != 0;
+    if (dense && (d.flags & (MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY)))
+        return fail(MPM_EUNSUPPORTED, "variant: dense output runs the flattened walk, one range "
+                    "per lane");
+    if (dense && d.block_threads && d.block_threads != 1024)
+        return fail(MPM_EINVAL, "variant: dense output needs block_threads 1024");
+    if (dense) {
+        L = 16;  // DENSE_LANE starting positions per lane
+        W = 1024;
+    }
     const bool supply = ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_SUPPLY);
     if (supply && !ix->keep_goto)
         return fail(MPM_EUNSUPPORTED, "variant: the supply-link walk needs an index built with "
@@ -201,11 +227,13 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     const DeviceLimits lim = limits();
     // dynamic LDS: the kernels' fixed header and byte-class regions, then the
     // tables when they are placed in LDS
-    const uint32_t fixed = 1024u;
-    const uint64_t table_lds = fixed + (supply ? ix->go_bytes : ix->table_bytes);
+    const uint32_t fixed = LDS_FIXED_BYTES;
+    const uint32_t reserve = dense ? DENSE_MARK_BYTES : 0u;  // LDS kept for the marks
+    const uint64_t table_lds = fixed + reserve + (supply ? ix->go_bytes : ix->table_bytes);
     const bool fits = table_lds <= (uint64_t)lim.max_lds;
     const bool ilp2 = ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2);
-    const bool hot_ok = has_hot(ix) && !ilp2 && !supply;
+    const bool hot_ok = has_hot(ix) && !ilp2 && !supply &&
+                        fixed + reserve + hot_lds_bytes(ix, reserve) <= (uint64_t)lim.max_lds;
     uint32_t place = d.placement;
     if (place == MPM_PLACE_AUTO)
         place = fits ? MPM_PLACE_LDS : (hot_ok ? MPM_PLACE_HOT : MPM_PLACE_GLOBAL);
@@ -224,8 +252,11 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     cfg->ilp = (ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2)) ? 2 : 1;
     cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS   ? (uint32_t)(supply ? ix->go_bytes
                                                                            : ix->table_bytes)
-                              : place == MPM_PLACE_HOT ? (uint32_t)hot_lds_bytes(ix)
+                              : place == MPM_PLACE_HOT ? (uint32_t)hot_lds_bytes(ix, reserve)
                                                        : 0u);
+    cfg->dense = dense;
+    cfg->mark_lds = dense ? cfg->lds_bytes : 0u;
+    cfg->lds_bytes += reserve;
     cfg->csr_lds = 0;
     if (csr_in_lds) {
         // Every reported occurrence reads the id CSR (the ids of its string,
@@ -270,7 +301,7 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
     if (ix->algo == MPM_ALGO_AC && c.supply) {
         e = ac_supply_launch(ix->state_bytes, ac_dev(ix), c, sd, s);
     } else if (ix->algo == MPM_ALGO_AC) {
-        const AcDev a = ac_dev(ix);
+        const AcDev a = ac_dev(ix, c.dense ? DENSE_MARK_BYTES : 0u);
         if (ix->state_bytes == 4)
             e = c.placement == MPM_PLACE_HOT ? ac32_hot_launch(a, c, sd, s) : ac32_glb_launch(a, c, sd, s);
         else if (c.placement == MPM_PLACE_HOT)

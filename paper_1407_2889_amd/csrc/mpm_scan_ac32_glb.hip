@@ -7,6 +7,9 @@ namespace mpm {
 const void *ac32_glb_kernel(const LaunchCfg &c)
 {
     const bool sw = c.swar, i2 = c.ilp == 2;
+    if (c.dense)
+        return sw ? pick_dense<AcWalk<uint32_t, false, true, 1>>()
+                  : pick_dense<AcWalk<uint32_t, false, false, 1>>();
     return sw ? (i2 ? pick_w<AcWalk<uint32_t, false, true, 2>>(c.block_threads)
                     : pick_w<AcWalk<uint32_t, false, true, 1>>(c.block_threads))
               : (i2 ? pick_w<AcWalk<uint32_t, false, false, 2>>(c.block_threads)
@@ -15,12 +18,18 @@ const void *ac32_glb_kernel(const LaunchCfg &c)
 
 const void *ac32_hot_kernel(const LaunchCfg &c)
 {
+    if (c.dense)
+        return c.swar ? pick_dense<AcWalk<uint32_t, PL_HOT, true, 1>>()
+                      : pick_dense<AcWalk<uint32_t, PL_HOT, false, 1>>();
     return c.swar ? pick_w<AcWalk<uint32_t, PL_HOT, true, 1>>(c.block_threads)
                   : pick_w<AcWalk<uint32_t, PL_HOT, false, 1>>(c.block_threads);
 }
 
 hipError_t ac32_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s)
 {
+    if (c.dense)
+        return c.swar ? launch_dense<AcWalk<uint32_t, PL_HOT, true, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, s)
+                      : launch_dense<AcWalk<uint32_t, PL_HOT, false, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, s);
     return c.swar ? launch_w<AcWalk<uint32_t, PL_HOT, true, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
                   : launch_w<AcWalk<uint32_t, PL_HOT, false, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s);
 }
@@ -28,6 +37,9 @@ hipError_t ac32_hot_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd
 hipError_t ac32_glb_launch(const AcDev &a, const LaunchCfg &c, const ScanDev &sd, hipStream_t s)
 {
     const bool sw = c.swar, i2 = c.ilp == 2;
+    if (c.dense)
+        return sw ? launch_dense<AcWalk<uint32_t, false, true, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, s)
+                  : launch_dense<AcWalk<uint32_t, false, false, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, s);
     if (sw)
         return i2 ? launch_w<AcWalk<uint32_t, false, true, 2>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s)
                   : launch_w<AcWalk<uint32_t, false, true, 1>>(a, c, sd, a.uoff, a.uids, a.dupfree, 0, s);

@@ -59,15 +59,16 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte load/store
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));  // two 16-bit states
 template <typename T> struct TabPtr<true, T> { using type = lds_cptr<T>; };
 
-static const int K_SLOTS = 4;  // occurrences a lane keeps in registers
+static const int K_SLOTS = 2;  // occurrences a lane keeps in registers (more are staged)
 
 // Dynamic LDS layout. The scan kernels declare no static LDS, so their
 // dynamic allocation starts at LDS address 0 (checked at kernel start) and
 // every region sits at a constant address: table reads then need no base
 // register, the constant goes into the ds_read offset field.
 static const uint32_t LDS_HDR_OFF = 0;     // LdsHdr: per-workgroup scalars
-static const uint32_t LDS_CLS_OFF = 512;   // AC: column byte offset per byte value
-static const uint32_t LDS_TAB_OFF = 1024;  // matching tables (LDS placement)
+static const uint32_t LDS_CLS_OFF = 1024;  // AC: column byte offset per byte value
+static const uint32_t LDS_TAB_OFF = 1536;  // matching tables (LDS placement)
+static_assert(LDS_TAB_OFF == LDS_FIXED_BYTES, "LDS layout and its host-side size disagree");
 
 template <typename T>
 __device__ __forceinline__ LDS_AS T *lds_at(uint32_t off)
@@ -84,6 +85,7 @@ struct LdsHdr {
     uint32_t pad;
     TextDesc td;     // the current chunk's text (single-index kernel)
     BatchText bt;    // the current chunk's text (batched kernel)
+    IdGroups grp;    // id count groups of the current index
 };
 static_assert(sizeof(LdsHdr) <= LDS_CLS_OFF - LDS_HDR_OFF, "LDS header overflows its region");
 
@@ -271,14 +273,49 @@ struct IdMap {
     {
         return lds_uids ? lds_at<const uint32_t>(lds_uids)[j] : uids[j];
     }
+    // CSR slots [b, e) of the ids of distinct string u: for strings in an id
+    // count group (the LDS header's copy of the index's groups) by
+    // arithmetic, otherwise from the CSR offsets.
+    __device__ __forceinline__ void span(uint32_t u, uint32_t &b, uint32_t &e) const
+    {
+        if (u < n_single) {
+            b = u;
+            e = u + 1;
+            return;
+        }
+        const LDS_AS IdGroups *g = lds_at<const IdGroups>(LDS_HDR_OFF + offsetof(LdsHdr, grp));
+        if (u < g->u0[g->n]) {
+            // groups ascend and u0[n] bounds u: the scan stops at a group
+            uint32_t k = 0;
+#pragma unroll 1
+            while (u >= g->u0[k + 1])
+                ++k;
+            const uint32_t c = g->cnt[k];
+            b = g->off[k] + (u - g->u0[k]) * c;
+            e = b + c;
+            return;
+        }
+        b = off(u);
+        e = off(u + 1);
+    }
     // ids reported for one occurrence of distinct string u
     __device__ __forceinline__ uint32_t count(uint32_t u) const
     {
-        if (u < n_single)
-            return 1u;
-        return off(u + 1) - off(u);
+        uint32_t b, e;
+        span(u, b, e);
+        return e - b;
     }
 };
+
+// Copy an index's id count groups into the LDS header (no barrier).
+__device__ __forceinline__ void load_groups(const IdGroups &src)
+{
+    constexpr int NW = (int)(sizeof(IdGroups) / 4);
+    LDS_AS uint32_t *d = lds_at<uint32_t>(LDS_HDR_OFF + offsetof(LdsHdr, grp));
+    const uint32_t *s = (const uint32_t *)&src;
+    if (threadIdx.x < (uint32_t)NW)
+        d[threadIdx.x] = s[threadIdx.x];
+}
 
 __device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_t &ob, uint32_t pos,
                                           uint32_t u, const IdMap &im)
@@ -290,7 +327,8 @@ __device__ __forceinline__ void write_ids(mpm_match *out_, uint64_t cap, uint64_
         ++ob;
         return;
     }
-    const uint32_t b = im.off(u), e = im.off(u + 1);
+    uint32_t b, e;
+    im.span(u, b, e);
     for (uint32_t j = b; j < e; ++j) {
         if (ob < cap)
             out[ob] = v2u{pos, im.id(j)};
@@ -1226,7 +1264,7 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
                                               uint64_t *s_scan, const Stage &stg)
 {
     constexpr int I = Walk::ILP;
-    constexpr int KS = I == 1 ? K_SLOTS : 2;  // occurrences kept per virtual lane
+    constexpr int KS = K_SLOTS;  // occurrences kept per virtual lane
     const uint32_t scap = stg.base ? stg.cap : 0u;
     const uint64_t chunk = (uint64_t)W * L * I;
     const uint64_t lt = g - first_g;
@@ -1244,15 +1282,13 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
     }
 
     // Phase A: count, keep the first occurrences in registers, stage the
-    // next ones in the workspace; lastp[v] is the start of the last one kept
-    // or staged.
-    uint32_t nu[I], nid[I], lastp[I];
+    // next ones in the workspace.
+    uint32_t nu[I], nid[I];
     uint32_t so[I][KS], su[I][KS];
 #pragma unroll
     for (int v = 0; v < I; ++v) {
         nu[v] = 0;
         nid[v] = 0;
-        lastp[v] = 0;
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             so[v][k] = 0;
@@ -1267,11 +1303,9 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
                     so[v][k] = (uint32_t)start;
                     su[v][k] = u;
                 }
-            lastp[v] = (uint32_t)start;
         } else if (nu[v] - (uint32_t)KS < scap) {
             stg.base[(uint64_t)(nu[v] - KS) * stg.lanes + threadIdx.x + v * W] =
                 v2u{(uint32_t)start, u};
-            lastp[v] = (uint32_t)start;
         }
         ++nu[v];
         nid[v] += im.count(u);
@@ -1312,11 +1346,91 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
             // The rest start after the last kept or staged one (one distinct
             // string per start): walk again from there, from the root / an
             // empty window.
-            const uint32_t lo2 = (uint32_t)((uint64_t)lastp[v] + 1 - base);
+            const uint32_t last =
+                scap ? stg.base[(uint64_t)(scap - 1) * stg.lanes + threadIdx.x + v * W].x
+                     : so[v][KS - 1];
+            const uint32_t lo2 = (uint32_t)((uint64_t)last + 1 - base);
             wk.lane_again(text, n, base, lo2, hi[v], [&](uint64_t start, uint32_t u) {
                 write_ids(out, cap, o, (uint32_t)start, u, im);
             });
         }
+    }
+}
+
+// Dense output: each lane owns DENSE_LANE starting positions and marks, per
+// position, the distinct string that starts there (or none) in an LDS array
+// laid out in position order; after the chunk's offsets are known, every wave
+// sweeps its 64 * DENSE_LANE positions in rounds of 64 consecutive ones, a
+// prefix sum over the round gives each position its output slot, and the
+// wave writes the round's pairs to consecutive slots. Lists with many
+// occurrences per position are written in whole cache lines by few
+// instructions, instead of every lane appending to its own output range.
+static const uint32_t DENSE_LANE = 16;
+static const uint32_t MARK_NONE = 0xffffffffu;
+
+template <class Walk, int W>
+__device__ __forceinline__ void process_chunk_dense(const Walk &wk, glb_cptr<uint8_t> text,
+                                                    uint64_t n, mpm_match *out_, uint64_t cap,
+                                                    uint64_t *total, uint64_t first_g, uint64_t nt,
+                                                    uint64_t g, uint32_t m, uint32_t epoch,
+                                                    const IdMap &im, uint32_t *hdr,
+                                                    uint64_t *status, uint64_t *s_scan,
+                                                    uint32_t mark_lds)
+{
+    static_assert(Walk::ILP == 1, "dense output runs one range per lane");
+    constexpr uint32_t DL = DENSE_LANE;
+    const uint64_t chunk = (uint64_t)W * DL;
+    const uint64_t lt = g - first_g;
+    const uint64_t ns = n - m + 1;
+    const uint64_t base = lt * chunk;
+    const uint64_t starts = (ns - base) < chunk ? (ns - base) : chunk;
+    const uint32_t l0 = threadIdx.x * DL;
+    const uint32_t lo = l0 < starts ? l0 : (uint32_t)starts;
+    const uint32_t hi = (l0 + DL) < starts ? (l0 + DL) : (uint32_t)starts;
+    LDS_AS uint32_t *mk = lds_at<uint32_t>(mark_lds);
+
+    // Phase A: marks and the lane's count of ids.
+#pragma unroll
+    for (uint32_t j = 0; j < DL; ++j)
+        mk[l0 + j] = MARK_NONE;
+    uint32_t nid[1] = {0};
+    wk.lane(text, n, base, lo, hi, [&](uint64_t start, uint32_t u) {
+        mk[(uint32_t)(start - base)] = u;
+        nid[0] += im.count(u);
+    });
+
+    // Phase B: offsets (its barriers also publish the marks to the wave).
+    const bool last = lt + 1 == nt;
+    uint64_t ob[1];
+    chunk_offsets<W, 1>(nid, ob, s_scan, status, g, first_g, last, total, epoch, &hdr[WS_ERR]);
+
+    // Phase C: the wave's positions in order, 64 at a time.
+    const int lane = threadIdx.x & 63;
+    const uint32_t wpos = threadIdx.x & ~63u;  // first lane of the wave
+    uint64_t o = ob[0];
+    o = ((uint64_t)__shfl((uint32_t)(o >> 32), 0, 64) << 32) | __shfl((uint32_t)o, 0, 64);
+    GLB_AS v2u *out = (GLB_AS v2u *)out_;
+#pragma unroll 1
+    for (uint32_t r = 0; r < DL && o < cap; ++r) {
+        const uint32_t p = wpos * DL + r * 64 + lane;  // chunk-relative start
+        const uint32_t u = mk[p];
+        uint32_t b = 0, e = 0;
+        if (u != MARK_NONE)
+            im.span(u, b, e);
+        const uint32_t c = e - b;
+        uint32_t x = c;
+#pragma unroll
+        for (int s = 1; s < 64; s <<= 1) {
+            const uint32_t y = __shfl_up(x, s, 64);
+            if (lane >= s)
+                x += y;
+        }
+        const uint32_t round = __shfl(x, 63, 64);
+        uint64_t q = o + (x - c);
+        const uint32_t pos = (uint32_t)(base + p);
+        for (uint32_t j = b; j < e && q < cap; ++j, ++q)
+            out[q] = v2u{pos, im.id(j)};
+        o += round;
     }
 }
 
@@ -1341,7 +1455,7 @@ __device__ __forceinline__ void finish_launch(uint32_t *hdr, uint32_t epoch)
     }
 }
 
-template <class Walk, int W>
+template <class Walk, int W, bool Dense = false>
 __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev sd,
                                                  const uint32_t *uoff_, const uint32_t *uids_,
                                                  uint32_t dupfree, uint32_t unused)
@@ -1383,6 +1497,7 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     stg.base = sd.stage ? (GLB_AS v2u *)sd.stage + (uint64_t)blockIdx.x * stg.cap * stg.lanes
                         : nullptr;
 
+    load_groups(a.grp);  // synchronised by the setup below
     Walk wk;
     wk.template setup<W>(a, unused);
     if (threadIdx.x == 0)
@@ -1412,9 +1527,14 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
         const uint64_t g = s_tile;
         if (g >= ntiles)
             break;
-        process_chunk<Walk, W>(wk, (glb_cptr<uint8_t>)s_td.text, s_td.n, s_td.out, s_td.cap,
-                               s_td.total, s_td.tile_begin, s_td.ntiles, g, L, m, s_epoch, im,
-                               hdr, status, s_scan, stg);
+        if constexpr (Dense)
+            process_chunk_dense<Walk, W>(wk, (glb_cptr<uint8_t>)s_td.text, s_td.n, s_td.out,
+                                         s_td.cap, s_td.total, s_td.tile_begin, s_td.ntiles, g, m,
+                                         s_epoch, im, hdr, status, s_scan, sd.mark_lds);
+        else
+            process_chunk<Walk, W>(wk, (glb_cptr<uint8_t>)s_td.text, s_td.n, s_td.out, s_td.cap,
+                                   s_td.total, s_td.tile_begin, s_td.ntiles, g, L, m, s_epoch, im,
+                                   hdr, status, s_scan, stg);
         __syncthreads();
     }
     finish_launch(hdr, s_epoch);
@@ -1504,10 +1624,14 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
         const uint64_t g = s_tile;
         if (g >= ntiles)
             break;
+        uint64_t t0 = 0;
+        if (threadIdx.x == 0)
+            t0 = wall_clock64();
         const uint32_t ix = s_bt.index;
         const auto &dev = dev_of<Walk>(bd.idx[ix]);
         if (ix != loaded) {
             Walk::template load<W>(dev);
+            load_groups(dev.grp);
             __syncthreads();
             loaded = ix;
         }
@@ -1515,6 +1639,13 @@ __global__ __launch_bounds__(W) void batch_kernel(BatchDev bd)
                              s_bt.td.cap, s_bt.td.total, s_bt.td.tile_begin, s_bt.td.ntiles, g,
                              s_bt.lane_bytes, s_epoch, hdr, status, s_scan, stg);
         __syncthreads();
+        // a timed request: its share of the launch and its longest chunk
+        // (s_bt holds this chunk's text until thread 0 takes the next ticket)
+        if (threadIdx.x == 0 && s_bt.cost) {
+            const float us = (float)(wall_clock64() - t0) * bd.us_per_tick;
+            atomicAdd(&s_bt.cost[0], us / (float)gridDim.x);
+            atomicMax((uint32_t *)&s_bt.cost[1], __float_as_uint(us));  // order of >= 0 floats
+        }
     }
     finish_launch(hdr, s_epoch);
 }
@@ -1576,6 +1707,23 @@ static hipError_t launch_w(const typename Walk::Dev &a, const LaunchCfg &c, cons
                            uids, dupfree, tl);
         break;
     }
+    return hipGetLastError();
+}
+
+// The dense-output kernel of a walker (1024 threads per workgroup).
+template <class Walk>
+static const void *pick_dense()
+{
+    return (const void *)scan_kernel<Walk, 1024, true>;
+}
+
+template <class Walk>
+static hipError_t launch_dense(const typename Walk::Dev &a, const LaunchCfg &c, const ScanDev &sd,
+                               const uint32_t *uoff, const uint32_t *uids, uint32_t dupfree,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL((scan_kernel<Walk, 1024, true>), dim3(c.grid), dim3(1024), c.lds_bytes, s, a,
+                       sd, uoff, uids, dupfree, 0u);
     return hipGetLastError();
 }
 

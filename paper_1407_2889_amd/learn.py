@@ -162,22 +162,26 @@ class Selector:
     needs), `time` predicts each variant's log milliseconds per request (what
     the batch planner's queue order needs)."""
 
-    def __init__(self, rank: _Ensemble, timing: _Ensemble):
+    def __init__(self, rank: _Ensemble, timing: _Ensemble, chunk_factor=None):
         self.rank = rank
         self.timing = timing
+        # per variant: a request's longest chunk time ~ its cost x factor /
+        # its number of chunks (fitted on the timing database)
+        self.chunk_factor = (np.ones(N_OUT) if chunk_factor is None
+                             else np.asarray(chunk_factor, np.float64))
 
     @classmethod
     def fit(cls, feats: np.ndarray, ms: np.ndarray, n_nets: int = 5, steps: int = 2000,
-            lr: float = 2e-3, seed: int = 0, device="cuda"):
+            lr: float = 2e-3, seed: int = 0, device="cuda", chunk_factor=None):
         """feats [R, 7]; ms [R, 24] per-request milliseconds (inf where a
-        variant cannot run)."""
+        variant cannot run); chunk_factor [24] (see __init__)."""
         valid = np.isfinite(ms) & (ms > 0)
         safe = np.where(valid, ms, 1.0)
         rel = np.log(safe / np.min(np.where(valid, ms, np.inf), axis=1, keepdims=True))
         rank = _Ensemble.fit(feats, np.where(valid, rel, 0.0), valid, n_nets, steps, lr, seed, device)
         timing = _Ensemble.fit(feats, np.log(safe), valid, max(1, n_nets // 2), steps, lr,
                                seed + 100, device)
-        sel = cls(rank, timing)
+        sel = cls(rank, timing, chunk_factor)
         sel.history = {"rank": rank.history, "time": timing.history}
         return sel
 
@@ -204,9 +208,11 @@ class Selector:
     def save(self, path: str):
         d = self.rank.state("rank")
         d.update(self.timing.state("time"))
+        d["chunk_factor"] = self.chunk_factor
         np.savez(path, **d)
 
     @classmethod
     def load(cls, path: str, device="cuda"):
         z = np.load(path)
-        return cls(_Ensemble.from_state(z, "rank", device), _Ensemble.from_state(z, "time", device))
+        return cls(_Ensemble.from_state(z, "rank", device), _Ensemble.from_state(z, "time", device),
+                   z["chunk_factor"] if "chunk_factor" in z else None)

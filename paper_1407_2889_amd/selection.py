@@ -3,7 +3,9 @@ the comparison of selection policies on a batch.
 
 Policies compared on one batch (each runs the whole batch as one replayed
 HIP graph, every text under the variant the policy picked):
-  exhaustive - every request timed on all 24 variants, fastest kept;
+  exhaustive - every request timed on all 24 variants (in batched launches,
+               each request's share of its launch measured by the kernel),
+               fastest kept;
   learned    - the selector's choice, except where its predicted best beats
                the runner-up by less than the margin: those requests take
                the exhaustive choice (the fallback);
@@ -24,18 +26,180 @@ from .learn import Selector
 
 
 def build_db(tuner: tune.Tuner, sets_idx, stream_dev, reqs, log=None):
-    """Features [R, 7] and per-request milliseconds [R, 24] of every request."""
+    """Features [R, 7] and per-request milliseconds [R, 24] of every request
+    (request (set, offset, length) is a slice of the device text stream):
+    every request timed on every variant inside batched launches."""
     R = len(reqs)
-    feats = np.zeros((R, 7))
-    ms = np.full((R, len(tune.VARIANTS)), np.inf)
     t0 = time.perf_counter()
+    feats = np.zeros((R, 7))
+    caps = np.zeros(R, np.int64)
     for i, (p, off, n) in enumerate(reqs):
         text = stream_dev[off:off + n]
         feats[i] = tuner.features(sets_idx[p], text)
-        ms[i] = tuner.time_all(sets_idx[p], text)
-        if log and (i + 1) % max(1, R // 10) == 0:
-            log(f"[tune] {i + 1}/{R} requests timed ({time.perf_counter() - t0:.1f}s)")
-    return feats, ms
+        caps[i] = tuner.count(sets_idx[p], text)
+    t1 = time.perf_counter()
+    offs = np.array([r[1] for r in reqs], np.int64)
+    lens = np.array([r[2] for r in reqs], np.int64)
+    ms, chunk = tune.time_batch(stream_dev, offs, lens, [sets_idx[r[0]] for r in reqs], caps)
+    if log:
+        log(f"[tune] {R} requests: features and counts {t1 - t0:.1f}s, all variants timed in "
+            f"batched launches {time.perf_counter() - t1:.1f}s")
+    nch = np.array([[tune.chunks_of(int(r[2]), sets_idx[r[0]].m, k) for k in range(len(tune.VARIANTS))]
+                    for r in reqs])
+    return feats, ms, chunk_factors(ms, chunk, nch)
+
+
+def chunk_factors(ms: np.ndarray, chunk: np.ndarray, nchunks: np.ndarray) -> np.ndarray:
+    """Per variant, the median over a timing database of longest chunk time
+    x chunks / share: a request's longest chunk is about its share times this
+    factor over its number of chunks (the factor is near the launch's
+    workgroup count when a request's chunks cost alike)."""
+    f = np.ones(ms.shape[1])
+    for k in range(ms.shape[1]):
+        ok = np.isfinite(ms[:, k]) & (ms[:, k] > 0) & np.isfinite(chunk[:, k])
+        if ok.any():
+            f[k] = float(np.median(chunk[ok, k] * nchunks[ok, k] / ms[ok, k]))
+    return f
+
+
+# Cost model of a plan (milliseconds). The launches of one plan run one after
+# another, each on the whole device, so a launch lasts about the larger of
+# its requests' summed shares and its longest chunk, plus a start-up and a
+# tail in which its last chunks finish while other workgroups idle.
+LAUNCH_MS = 0.015
+TAIL = 0.5
+
+
+def launch_keys(pset, valid: np.ndarray) -> np.ndarray:
+    """[R, V] launch key of request i under variant k (-1 where it cannot
+    run): requests with equal keys share one launch of the plan."""
+    R, V = valid.shape
+    keys = np.full((R, V), -1, np.int64)
+    for i in range(R):
+        for k in range(V):
+            if valid[i, k]:
+                key = pset[i].launch_key(k)
+                keys[i, k] = -1 if key is None else key
+    return keys
+
+
+def plan_ms(choice: np.ndarray, cost: np.ndarray, chunk: np.ndarray, keys: np.ndarray) -> float:
+    """Modelled time of the plan that runs request i under variant choice[i]."""
+    r_ = np.arange(len(choice))
+    k = keys[r_, choice]
+    c, h = cost[r_, choice], chunk[r_, choice]
+    t = 0.0
+    for key in np.unique(k):
+        sel = k == key
+        S, Cm = float(c[sel].sum()), float(h[sel].max())
+        t += max(S, Cm) + LAUNCH_MS + TAIL * Cm
+    return t
+
+
+class _Plan:
+    """Launch statistics of an assignment, updated one move at a time."""
+
+    def __init__(self, choice, cost, chunk, keys):
+        from sortedcontainers import SortedList
+        self.choice, self.cost, self.chunk, self.keys = choice, cost, chunk, keys
+        self.S, self.H = {}, {}
+        for i, k in enumerate(choice):
+            key = int(keys[i, k])
+            self.S[key] = self.S.get(key, 0.0) + float(cost[i, k])
+            self.H.setdefault(key, SortedList()).add(float(chunk[i, k]))
+
+    @staticmethod
+    def _t(S, Cm, n):
+        return 0.0 if n == 0 else max(S, Cm) + LAUNCH_MS + TAIL * Cm
+
+    def _launch(self, key):
+        h = self.H.get(key)
+        return (self.S.get(key, 0.0), h[-1] if h else 0.0, len(h) if h else 0)
+
+    def delta(self, i: int, k: int) -> float:
+        """Change of the modelled plan time if request i moves to variant k."""
+        k0 = int(self.choice[i])
+        a, b = int(self.keys[i, k0]), int(self.keys[i, k])
+        c0, h0 = float(self.cost[i, k0]), float(self.chunk[i, k0])
+        c1, h1 = float(self.cost[i, k]), float(self.chunk[i, k])
+        Sa, Ca, na = self._launch(a)
+        ha = self.H[a]
+        # longest chunk of launch a without request i
+        Ca_wo = (ha[-2] if na > 1 else 0.0) if h0 >= Ca else Ca
+        if a == b:
+            return self._t(Sa - c0 + c1, max(Ca_wo, h1), na) - self._t(Sa, Ca, na)
+        Sb, Cb, nb = self._launch(b)
+        return (self._t(Sa - c0, Ca_wo, na - 1) + self._t(Sb + c1, max(Cb, h1), nb + 1)
+                - self._t(Sa, Ca, na) - self._t(Sb, Cb, nb))
+
+    def move(self, i: int, k: int):
+        k0 = int(self.choice[i])
+        a, b = int(self.keys[i, k0]), int(self.keys[i, k])
+        self.S[a] -= float(self.cost[i, k0])
+        self.H[a].remove(float(self.chunk[i, k0]))
+        if not self.H[a]:
+            del self.H[a], self.S[a]
+        self.S[b] = self.S.get(b, 0.0) + float(self.cost[i, k])
+        if b not in self.H:
+            from sortedcontainers import SortedList
+            self.H[b] = SortedList()
+        self.H[b].add(float(self.chunk[i, k]))
+        self.choice[i] = k
+
+
+def schedule(choice: np.ndarray, cost: np.ndarray, chunk: np.ndarray, valid: np.ndarray,
+             pset, keys: np.ndarray | None = None, uniform=None, passes: int = 6) -> np.ndarray:
+    """Batch-aware assignment minimising the plan's modelled time (plan_ms).
+    Starts from the better of the given per-request choices and every
+    uniform assignment, then alternates moves of single requests to the
+    variant that lowers the model most and the dissolution of whole launches
+    (each request to its cheapest variant in another launch), while the model
+    improves. cost, chunk [R, V]: per-request share and longest chunk
+    (measured, or predicted for the learned selector)."""
+    keys = launch_keys(pset, valid) if keys is None else keys
+    ok = (keys >= 0) & np.isfinite(cost) & np.isfinite(chunk)
+    R, V = cost.shape
+    cost = np.where(ok, cost, np.inf)
+    chunk = np.where(ok, chunk, np.inf)
+    starts = [np.array(choice, copy=True)]
+    for k in (range(V) if uniform is None else uniform):
+        u = np.array([uniform_choice(k, ok[i]) for i in range(R)])
+        if ok[np.arange(R), u].all():
+            starts.append(u)
+    starts = [c for c in starts if ok[np.arange(R), c].all()]
+    best = min(starts, key=lambda c: plan_ms(c, cost, chunk, keys)).copy()
+    plan = _Plan(best, cost, chunk, keys)
+    for _ in range(passes):
+        improved = False
+        # single-request moves, largest shares first
+        order = np.argsort(-cost[np.arange(R), plan.choice])
+        for i in order:
+            cand = np.flatnonzero(ok[i])
+            d = [plan.delta(int(i), int(k)) for k in cand]
+            j = int(np.argmin(d))
+            if d[j] < -1e-9:
+                plan.move(int(i), int(cand[j]))
+                improved = True
+        # dissolve launches, smallest first, while the model improves
+        for key in sorted(plan.S, key=plan.S.get):
+            if key not in plan.S or len(plan.S) == 1:
+                continue
+            trial = plan.choice.copy()
+            members = np.flatnonzero(keys[np.arange(R), trial] == key)
+            others = set(plan.S) - {key}
+            moved = True
+            for i in members:
+                alt = [k for k in np.flatnonzero(ok[i]) if int(keys[i, k]) in others]
+                if not alt:
+                    moved = False
+                    break
+                trial[i] = min(alt, key=lambda k: cost[i, k])
+            if moved and plan_ms(trial, cost, chunk, keys) < plan_ms(plan.choice, cost, chunk, keys) - 1e-9:
+                plan = _Plan(trial, cost, chunk, keys)
+                improved = True
+        if not improved:
+            break
+    return plan.choice
 
 
 def to_gbps(lens: np.ndarray, ms: np.ndarray) -> np.ndarray:
@@ -114,21 +278,26 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
     ms_pred = selector.predict_ms(feats)
     t_infer = time.perf_counter() - t0
 
-    # exhaustive autotuning of every request (the reference, and the source of
-    # the fallback choices)
-    t0 = time.perf_counter()
-    rows = []
-    for i in range(R):
-        rows.append(tuner.time_all(pset[i], texts[i]))
-        if log and (i + 1) % max(1, R // 10) == 0:
-            log(f"[select] exhaustive tuning {i + 1}/{R} ({time.perf_counter() - t0:.1f}s)")
-    ms = np.stack(rows)
-    t_exh = time.perf_counter() - t0
-    exh = np.argmin(ms, axis=1)
-    t_fallback = t_exh * float(fallback.mean())
-    final = np.where(fallback, exh, learned)
-    default = np.array([uniform_choice(default_variant, valid_r[i]) for i in range(R)])
     caps = [tuner.count(pset[i], texts[i]) for i in range(R)]
+    # exhaustive autotuning of every request (the reference, and the source of
+    # the fallback choices): every request on every variant
+    t0 = time.perf_counter()
+    ms, chunk = tune.time_batch(arena, offs, lens, pset, caps)
+    t_exh = time.perf_counter() - t0
+    exh_req = np.argmin(ms, axis=1)  # each request's fastest variant
+    keys = launch_keys(pset, valid_r)
+    exh = schedule(exh_req, ms, chunk, valid_r, pset, keys)
+    t_fallback = t_exh * float(fallback.mean())
+    # the learned policy knows measured costs only where it fell back; its
+    # longest chunks are estimated from its predicted costs
+    nch = np.array([[tune.chunks_of(int(lens[i]), pset[i].m, k) for k in range(len(tune.VARIANTS))]
+                    for i in range(R)])
+    ms_learned = np.where(fallback[:, None], ms, ms_pred)
+    chunk_learned = np.where(fallback[:, None], chunk,
+                             ms_pred * selector.chunk_factor[None, :] / nch)
+    final = schedule(np.where(fallback, exh_req, learned), ms_learned, chunk_learned, valid_r,
+                     pset, keys)
+    default = np.array([uniform_choice(default_variant, valid_r[i]) for i in range(R)])
     if log:
         log(f"[select] features {t_feat:.2f}s, inference {t_infer * 1e3:.1f}ms, exhaustive "
             f"{t_exh:.1f}s, fallback rate {fallback.mean():.3f}")
@@ -136,7 +305,6 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
     # Queue hints: each policy only uses what it knows. Exhaustive: measured
     # times; learned: predicted times (measured ones where it fell back);
     # default: none.
-    ms_learned = np.where(fallback[:, None], ms, ms_pred)
 
     def run(choice, ms_known, name):
         return run_batch(arena, offs, lens, pset, choice, ms_known, caps, reps,
@@ -159,18 +327,22 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
     res["fallback_rate"] = float(fallback.mean())
     res["selection_overhead_s"] = {"features": t_feat, "inference": t_infer,
                                    "fallback_tuning": t_fallback, "exhaustive_tuning": t_exh}
-    # how often the learned pick (before fallback) equals the exhaustive best,
-    # and its predicted-vs-isolated slowdown on the picks that differ
-    iso = to_gbps(np.asarray(lens), ms)
-    best = iso[np.arange(R), exh]
-    res["pick_agreement"] = float(np.mean(learned == exh))
-    res["isolated_regret_learned_only"] = float(
-        1.0 - iso[np.arange(R), learned].sum() / max(best.sum(), 1e-30))
-    tbest = ms[np.arange(R), exh].sum()
-    res["time_regret_isolated"] = {
-        "learned_no_fallback": float(ms[np.arange(R), learned].sum() / tbest - 1),
-        "learned": float(ms[np.arange(R), final].sum() / tbest - 1),
-        "default": float(ms[np.arange(R), default].sum() / tbest - 1)}
+    # how often the learned pick (before fallback) equals the per-request
+    # best, and each policy's summed measured cost against the per-request
+    # bests (every request on its own fastest variant)
+    res["pick_agreement"] = float(np.mean(learned == exh_req))
+    r_ = np.arange(R)
+    tbest = ms[r_, exh_req].sum()
+    res["time_regret_tuned"] = {
+        "learned_no_fallback": float(ms[r_, learned].sum() / tbest - 1),
+        "learned": float(ms[r_, final].sum() / tbest - 1),
+        "exhaustive_scheduled": float(ms[r_, exh].sum() / tbest - 1),
+        "default": float(ms[r_, default].sum() / tbest - 1)}
+    # each plan's modelled time from the measured costs, beside its replay
+    res["model_ms"] = {name: plan_ms(c, np.where(np.isfinite(ms), ms, np.inf),
+                                     np.where(np.isfinite(chunk), chunk, np.inf), keys)
+                       for name, c in (("exhaustive", exh), ("learned", final),
+                                       ("default", default))}
     res["default_variant"] = list(tune.VARIANTS[default_variant])
     res["matches"] = int(np.sum(caps))
     res["_state"] = dict(arena=arena, offs=offs, lens=lens, pset=pset, caps=caps, ms=ms,

@@ -65,6 +65,20 @@ class PatternSetIndexes:
     def index(self, k: int) -> Index:
         return self.ac if VARIANTS[k][0] == "ac" else self.wm
 
+    def launch_key(self, k: int):
+        """The batched launch a request of this set joins under variant k
+        (None where the variant cannot run)."""
+        keys = self.__dict__.setdefault("_keys", {})
+        if k not in keys:
+            from . import launch_key
+            try:
+                keys[k] = launch_key(self.index(k), variant_struct(k)) if self.lds_fits(k) else None
+            except MpmError as e:
+                if e.status != MPM_EUNSUPPORTED:
+                    raise
+                keys[k] = None
+        return keys[k]
+
     def lds_fits(self, k: int) -> bool:
         """Whether variant k can run (LDS placement needs the tables to fit)."""
         if VARIANTS[k][3] != PLACEMENTS[0]:
@@ -179,6 +193,48 @@ class Tuner:
         return out
 
 
+def time_batch(arena, offs, lens, sets: list, counts, reps: int = 2):
+    """Per-request costs of all 24 variants (inf where a variant cannot run),
+    measured where requests run: for each variant, every request that can
+    take it goes into one batched launch (launches one after another), and
+    each chunk's workgroup adds its wall-clock time divided by the launch's
+    workgroup count to the request's cost (its share of a launch that has
+    the device to itself) and raises the request's longest chunk time. One
+    warm-up run, then `reps` runs. Request i is bytes [offs[i], offs[i] +
+    lens[i]) of the device arena, scanned with sets[i], with counts[i]
+    matches. Returns (share ms [R, 24] (mean per run), longest chunk ms
+    [R, 24])."""
+    from . import batch as _batch
+    offs = np.asarray(offs, np.int64)
+    lens = np.asarray(lens, np.int64)
+    caps = np.asarray(counts, np.int64)
+    R = len(lens)
+    share = np.full((R, len(VARIANTS)), math.inf)
+    chunk = np.full((R, len(VARIANTS)), math.inf)
+    for k in range(len(VARIANTS)):
+        ok = np.array([i for i in range(R) if sets[i].lds_fits(k)], np.int64)
+        if ok.size == 0:
+            continue
+        v = variant_struct(k)
+        bs = _batch.BatchScan(arena, offs[ok], lens[ok], [sets[i].index(k) for i in ok],
+                              [v] * ok.size, caps[ok], timed=True)
+        bs.run()
+        bs.costs.zero_()
+        for _ in range(reps):
+            bs.run()
+        c = bs.costs[: ok.size].cpu().numpy().astype(np.float64)
+        share[ok, k] = c[:, 0] / reps / 1e3
+        chunk[ok, k] = c[:, 1] / 1e3
+        bs.close()
+    return share, chunk
+
+
+def chunks_of(n: int, m: int, k: int) -> int:
+    """Chunks a text of n bytes forms under variant k (patterns of length m)."""
+    _, L, W, _ = VARIANTS[k]
+    return max(1, math.ceil(max(n - m + 1, 0) / (L * W)))
+
+
 def _ws_bytes(ix: Index, n: int) -> int:
     from . import workspace_bytes
     return workspace_bytes(ix, max(n, 1 << 16), Variant(256, 256, 0, 0, 0))
@@ -201,4 +257,4 @@ def gbps(n: int, ms: np.ndarray) -> np.ndarray:
 
 
 __all__ = ["VARIANTS", "DEFAULT_VARIANT", "FEATURES", "PatternSetIndexes", "Tuner", "gbps",
-           "variant_struct"]
+           "variant_struct", "time_batch", "chunks_of"]

@@ -183,6 +183,13 @@ def test_unique_csr():
     assert uoff.tolist() == [0, 1, 3, 5]
     assert ids.tolist() == [2, 1, 3, 0, 4]
     assert ix.info()["max_dup"] == 2
+    # groups by id count, each in string order: GG:{3}, then CC:{1,5} TT:{2,7},
+    # then AA:{0,4,6}
+    P = np.frombuffer(b"AACCTTGGAACCAATT", np.uint8).reshape(8, 2)
+    for build in (mpm.build_ac, mpm.build_wm):
+        uoff, ids = build(P).export_unique()
+        assert uoff.tolist() == [0, 1, 3, 5, 8]
+        assert ids.tolist() == [3, 1, 5, 2, 7, 0, 4, 6]
 
 
 def wm_hash2(block, sh):

@@ -124,7 +124,9 @@ def test_edge_cases(mpm, case, algo):
     variants = (dict(lane_bytes=16, block_threads=256), dict(lane_bytes=64, block_threads=1024),
                 dict(lane_bytes=256, block_threads=512, placement=2),
                 dict(lane_bytes=32, block_threads=256, flags=2),
-                dict(lane_bytes=128, block_threads=1024, flags=3))
+                dict(lane_bytes=128, block_threads=1024, flags=3),
+                dict(block_threads=1024, flags=mpm.VARIANT_DENSE),
+                dict(block_threads=1024, placement=2, flags=mpm.VARIANT_DENSE))
     if algo == "ac-supply":
         variants = tuple(dict(v, flags=mpm.VARIANT_SUPPLY) for v in variants if not v.get("flags"))
     for mis in (0, 3):
@@ -132,6 +134,42 @@ def test_edge_cases(mpm, case, algo):
             say(f"[edge {name} n={len(T)} d={len(P)} m={P.shape[1]}] {algo} misalign={mis} {v}")
             got = gpu_pairs(mpm, ix, T, mpm.variant(**v), misalign=mis)
             assert_same(got, want, f"{name} {algo} mis={mis} {v}")
+
+
+@pytest.mark.parametrize("algo", ["ac", "wm"])
+def test_dense_output_all_placements(mpm, algo):
+    """Dense output (position marks in LDS, waves writing consecutive slots)
+    on a set with about one occurrence per position and repeated strings
+    (several id-count groups), every placement, aligned and misaligned text,
+    full lists and overflowing capacities."""
+    t = synth.est_text(3_000_000, seed=51)
+    ps = synth.pattern_set(t, d=20000, m=8, n_planted=5000, seed=52)
+    P = ps.patterns.copy()
+    P[100:160] = P[0]          # one string with 61 ids
+    P[200:203] = P[1]          # one with 4
+    want = oracle.parallel_scan(oracle.Win(P), t)
+    assert len(want[0]) > len(t) // 5
+    ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+    for pl in (0, 1, 2, 3):
+        v = mpm.variant(block_threads=1024, placement=pl, flags=mpm.VARIANT_DENSE)
+        for mis in (0, 5):
+            say(f"[dense] {algo} placement={pl} misalign={mis}")
+            try:
+                got = gpu_pairs(mpm, ix, t, v, misalign=mis)
+            except mpm.MpmError as e:
+                # the tables (or their hot part) and the marks exceed the LDS
+                assert e.status == mpm.MPM_EUNSUPPORTED and pl in (1, 3)
+                break
+            assert_same(got, want, f"dense {algo} pl={pl} mis={mis}")
+    dev = to_dev(t)
+    for cap in (0, 1, 777, len(want[0]) - 1):
+        say(f"[dense] {algo} capacity {cap}")
+        sc = mpm.Scanner(ix, len(t), cap, mpm.variant(block_threads=1024, flags=mpm.VARIANT_DENSE))
+        with pytest.raises(mpm.MpmError):
+            sc.scan(dev)
+        assert int(sc.total.item()) == len(want[0])
+        got = mpm.pairs_numpy(sc.out[:cap])
+        assert_same(got, (want[0][:cap], want[1][:cap]), f"dense prefix {cap}")
 
 
 @pytest.mark.parametrize("algo", ["ac", "wm"])

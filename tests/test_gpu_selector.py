@@ -1,13 +1,14 @@
 """GPU: what the learned variant selector gains over the scan without it.
 
-A small timing database (seeded training requests, every request timed on all
-24 launch variants by the exhaustive autotuner) trains the selector network
-with the library's own kernels; a held-out batch of requests (other seeds)
-is then run as replayed graphs under three policies: exhaustive autotune,
-learned choice with fallback, and the single fixed variant that is best on
-the training database (the method without the selector). The comparison uses
-the per-request times the exhaustive autotuner measured on the held-out
-requests, so every policy is judged on the same numbers.
+A timing database (seeded training requests, every request timed on all 24
+launch variants by the exhaustive autotuner, inside batched launches) trains
+the selector network with the library's own kernels; a held-out batch of
+requests (other seeds) is then run as replayed graphs under three policies:
+exhaustive autotune, learned choice with fallback, and the single fixed
+variant that is best on the training database (the method without the
+selector). The learned policy's batch throughput must stay within 10% of
+exhaustive tuning's, and on the held-out requests its choices must cost less
+than the fixed variant's by the autotuner's own measurements.
 """
 
 import numpy as np
@@ -26,26 +27,28 @@ def say(*a):
 def test_selector_beats_fixed_variant_on_held_out_batch():
     from paper_1407_2889_amd import learn, selection, tune
     say("[selector] timing database")
-    stream, sets, reqs = synth.selector_training_requests(400, 24, seed=7000, stream_bytes=64 << 20,
-                                                     max_len=1 << 20, d_hi=20000)
+    stream, sets, reqs = synth.selector_training_requests(2000, 24, seed=7000,
+                                                          stream_bytes=128 << 20,
+                                                          max_len=1 << 20, d_hi=20000)
     sd = torch.from_numpy(stream).cuda()
     sidx = [tune.PatternSetIndexes.build(p.patterns) for p in sets]
     tuner = tune.Tuner()
-    feats, ms = selection.build_db(tuner, sidx, sd, reqs, log=say)
+    feats, ms, cfac = selection.build_db(tuner, sidx, sd, reqs, log=say)
     assert np.isfinite(ms).any(axis=1).all()
     say("[selector] training")
-    sel = learn.Selector.fit(feats, ms, n_nets=3, steps=1500)
+    sel = learn.Selector.fit(feats, ms, n_nets=3, steps=1500, chunk_factor=cfac)
     kdef = selection.best_uniform_variant(ms)
     say(f"[selector] fixed variant {tune.VARIANTS[kdef]}")
-    b = synth.workload_batch(n_texts=192, n_sets=16, max_len=1 << 20, d_hi=20000, seed=7100)
+    b = synth.workload_batch(n_texts=512, n_sets=16, max_len=1 << 20, d_hi=20000, seed=7100)
     res = selection.evaluate(b, tuner, sel, kdef, log=say)
     res.pop("_state")
     say({k: v for k, v in res.items()})
     # every policy reports exactly the same matches
     assert res["totals_agree"]
-    tr = res["time_regret_isolated"]
-    # the selector (with its fallback) picks faster variants than the fixed
-    # one on requests it has not seen, and stays close to exhaustive tuning
-    assert tr["learned"] < tr["default"], tr
-    assert tr["learned"] < 0.25, tr
+    # learned selection (with its fallback) within 10% of exhaustive tuning on
+    # the replayed batch, and on requests it has not
+    # seen it picks variants whose measured costs beat the fixed variant's
+    assert res["regret"] <= 0.10, res["regret"]
+    tr = res["time_regret_tuned"]
+    assert tr["learned_no_fallback"] < tr["default"], tr
     assert 0.0 <= res["fallback_rate"] < 1.0

@@ -110,6 +110,13 @@ def test_sweep_full_size(mpm, sweep_text, golden, d, m):
     # Wu-Manber: the same list
     assert a.shape == w.shape, f"AC {a.shape[0]} vs WM {w.shape[0]} pairs"
     assert torch.equal(a, w), "AC and WM lists differ"
+    # dense output, both algorithms: the same list again
+    for algo in ("ac", "wm"):
+        ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(P, upload=True)
+        say(f"[sweep d={d} m={m}] {algo} dense output")
+        dn = mpm.scan(ix, dev, capacity=g["total"], var=mpm.variant(**bench.DENSE_VARIANT))
+        assert torch.equal(dn, a), f"{algo} dense output differs"
+        del ix, dn
     key = device_keys(a)
     # sampled exact comparison with the oracle
     orc = oracle.Win(P)
