@@ -39,7 +39,7 @@ def test_selector_beats_fixed_variant_on_held_out_batch():
     sel = learn.Selector.fit(feats, ms, n_nets=3, steps=1500, chunk_factor=cfac)
     kdef = selection.best_uniform_variant(ms)
     say(f"[selector] fixed variant {tune.VARIANTS[kdef]}")
-    b = synth.workload_batch(n_texts=512, n_sets=16, max_len=1 << 20, d_hi=20000, seed=7100)
+    b = synth.workload_batch(n_texts=1024, n_sets=16, max_len=2 << 20, d_hi=20000, seed=7100)
     res = selection.evaluate(b, tuner, sel, kdef, log=say)
     res.pop("_state")
     say({k: v for k, v in res.items()})

@@ -31,12 +31,15 @@ def brute_plan_ms(choice, cost, chunk, keys):
     launches = {}
     for i, k in enumerate(choice):
         launches.setdefault(int(keys[i, k]), []).append((cost[i, k], chunk[i, k]))
-    t = 0.0
+    total, excess, longest = 0.0, 0.0, 0.0
     for members in launches.values():
         S = sum(c for c, _ in members)
         Cm = max(h for _, h in members)
-        t += max(S, Cm) + selection.LAUNCH_MS + selection.TAIL * Cm
-    return t
+        total += S
+        excess += max(0.0, Cm - S)
+        longest = max(longest, Cm)
+    return max(total + selection.LAUNCH_MS * len(launches) + selection.EXCESS * excess,
+               selection.CHUNK * longest)
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
