@@ -130,7 +130,7 @@ typedef struct {
 /* Facts about a built index. */
 typedef struct {
     uint32_t algo;           /* MPM_ALGO_AC or MPM_ALGO_WM */
-    uint32_t m;              /* pattern length */
+    uint32_t m;              /* pattern length (the shortest, for several) */
     uint32_t d;              /* number of patterns */
     uint32_t d_unique;       /* distinct pattern strings */
     uint32_t max_dup;        /* most ids sharing one string */
@@ -143,6 +143,7 @@ typedef struct {
     double wm_mean_shift;    /* WM: mean SHIFT over all block hashes */
     uint64_t table_bytes;    /* bytes of the matching tables read by the scan loop */
     uint64_t device_bytes;   /* size of the device image (mpm_device_bytes) */
+    uint32_t m_max;          /* longest pattern (m when all lengths are equal) */
 } mpm_info;
 
 /* ---------------------------------------------------------------------- */
@@ -167,6 +168,37 @@ mpm_status mpm_build_ac(const uint8_t *patterns, uint32_t d, uint32_t m,
  * opts->wm_block is outside 1..min(m, 8). Host-only. */
 mpm_status mpm_build_wm(const uint8_t *patterns, uint32_t d, uint32_t m,
                         const mpm_opts *opts, mpm_index **out);
+
+/* Indexes over patterns of different lengths (the Definition of Section 1
+ * read with a length per pattern: (i, r) is reported when the |p^r| bytes at
+ * i equal p^r). A scan reports, per starting position, the ids of every
+ * pattern that occurs there, ascending, positions ascending, exactly as for
+ * one length; starting positions run over 0 .. n - (shortest length).
+ *   patterns: host bytes; pattern r is patterns[offsets[r] .. offsets[r + 1]).
+ *   offsets:  host, d + 1 ascending entries (every pattern non-empty).
+ * Wherever a distinct string occurs, so does every pattern that is a prefix
+ * of it: each distinct string's id list (mpm_export_unique) holds the ids of
+ * all of them, and a scan finds the longest string at each start.
+ * Aho-Corasick builds the automaton of the reversed strings, each state's
+ * output set merged with its supply state's (Section 3.1, Algorithm 2); a
+ * lane walks its range from the end, m_max - 1 bytes past it. Wu-Manber
+ * takes the shortest length as its window m and builds SHIFT, HASH and
+ * PREFIX from every pattern's first m bytes (Section 3.2); a bucket lists
+ * longer strings first and the first whole match at a window is reported.
+ * When all lengths are equal these return the index of mpm_build_ac /
+ * mpm_build_wm. Indexes of several lengths run in single-text scans
+ * (mpm_scan, mpm_scan_sync, mpm_scan_noalloc) with one range per lane and
+ * per-lane output: MPM_VARIANT_ILP2, _SUPPLY and _DENSE, batches, tuning and
+ * mpm_scan_host give EUNSUPPORTED, as does opts->ac_goto; the Aho-Corasick
+ * walk has no hot placement.
+ * Errors: EINVAL (null pointer, d == 0, an empty pattern or descending
+ * offsets), ETOOBIG (more than 2^31 automaton states, 4 GiB of distinct
+ * pattern bytes or 2^31 id-list entries), EUNSUPPORTED (wm_block outside
+ * 1..min(shortest length, 8)), ENOMEM. Host-only. */
+mpm_status mpm_build_ac_var(const uint8_t *patterns, const uint64_t *offsets, uint32_t d,
+                            const mpm_opts *opts, mpm_index **out);
+mpm_status mpm_build_wm_var(const uint8_t *patterns, const uint64_t *offsets, uint32_t d,
+                            const mpm_opts *opts, mpm_index **out);
 
 /* Release an index (host memory only; the caller owns the device image).
  * NULL is accepted. */
@@ -415,7 +447,9 @@ mpm_status mpm_mlp_adam(float *d_theta, const float *d_grad, float *d_m, float *
 
 /* Copy the dense Aho-Corasick table. Rows are states in breadth-first order
  * (root 0; the d_unique depth-m states last, state n_states - d_unique + u
- * being distinct string u of mpm_export_unique); columns are 1 + n_classes:
+ * being distinct string u of mpm_export_unique; for several lengths, the
+ * automaton of the reversed strings, states that report a string last);
+ * columns are 1 + n_classes:
  * column 0 (bytes in no pattern)
  * leads to the root, column c to the state after the c-th smallest pattern
  * byte. classes receives the n_classes bytes (may be NULL).
@@ -426,12 +460,13 @@ mpm_status mpm_export_ac(const mpm_index *idx, uint32_t *table, uint8_t *classes
 /* Copy the Wu-Manber SHIFT table (4^B uint8 entries). Errors: EINVAL. */
 mpm_status mpm_export_wm_shift(const mpm_index *idx, uint8_t *shift);
 
-/* Copy the unique-string index: uoff (d_unique + 1 entries) and ids (d
- * entries) so that ids[uoff[u] .. uoff[u+1]) are the ascending pattern ids of
- * distinct pattern string u. Distinct strings are numbered by how many ids
- * they stand for (those that occur once in the pattern array first, then
- * those that occur twice, and so on), each group in ascending string order.
- * Errors: EINVAL. */
+/* Copy the unique-string index: uoff (d_unique + 1 entries) and ids
+ * (uoff[d_unique] entries: d for one length) so that ids[uoff[u] .. uoff[u+1])
+ * are the ascending pattern ids reported where distinct pattern string u is
+ * found (its copies, and for several lengths every pattern that is a prefix
+ * of it). Distinct strings are numbered by how many ids they stand for (one
+ * first, then two, and so on), each group in ascending string order. Either
+ * pointer may be NULL. Errors: EINVAL. */
 mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids);
 
 /* ---------------------------------------------------------------------- */

@@ -80,7 +80,7 @@ class Info(C.Structure):
                 ("n_states", C.c_uint64), ("state_bytes", C.c_uint32), ("wm_block", C.c_uint32),
                 ("wm_code_shift", C.c_uint32), ("wm_zero_shift", C.c_uint32),
                 ("wm_mean_shift", C.c_double), ("table_bytes", C.c_uint64),
-                ("device_bytes", C.c_uint64)]
+                ("device_bytes", C.c_uint64), ("m_max", C.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -106,6 +106,8 @@ def _sig(name, res, args):
 _sig("mpm_last_error", C.c_char_p, [])
 _sig("mpm_version", C.c_char_p, [])
 _sig("mpm_build_ac", C.c_int32, [_vp, _u32, _u32, C.POINTER(Opts), _pvp])
+_sig("mpm_build_ac_var", C.c_int32, [_vp, _vp, _u32, C.POINTER(Opts), _pvp])
+_sig("mpm_build_wm_var", C.c_int32, [_vp, _vp, _u32, C.POINTER(Opts), _pvp])
 _sig("mpm_build_wm", C.c_int32, [_vp, _u32, _u32, C.POINTER(Opts), _pvp])
 _sig("mpm_free", None, [_vp])
 _sig("mpm_device_bytes", _u64, [_vp])
@@ -151,7 +153,8 @@ EXPORTS = [
     "mpm_export_wm_shift", "mpm_export_unique", "mpm_last_error", "mpm_version", "mpm_read_probe",
     "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
     "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam", "mpm_count_ids",
-    "mpm_scan_host", "mpm_scan_noalloc", "mpm_batch_launch_key",
+    "mpm_scan_host", "mpm_scan_noalloc", "mpm_batch_launch_key", "mpm_build_ac_var",
+    "mpm_build_wm_var",
 ]
 
 
@@ -239,9 +242,10 @@ class Index:
     def export_unique(self):
         inf = self.info()
         uoff = np.empty(inf["d_unique"] + 1, np.uint32)
-        ids = np.empty(inf["d"], np.uint32)
-        _check(_L.mpm_export_unique(self._h, uoff.ctypes.data, ids.ctypes.data), "mpm_export_unique")
-        return uoff, ids
+        _check(_L.mpm_export_unique(self._h, uoff.ctypes.data, None), "mpm_export_unique")
+        ids = np.empty(max(1, int(uoff[-1])), np.uint32)
+        _check(_L.mpm_export_unique(self._h, None, ids.ctypes.data), "mpm_export_unique")
+        return uoff, ids[:int(uoff[-1])]
 
     def close(self):
         if self._h:
@@ -279,6 +283,43 @@ def build_wm(patterns, B: int = 0, upload: bool = False) -> Index:
     Pp = P if P.size else np.zeros(1, np.uint8)
     _check(_L.mpm_build_wm(Pp.ctypes.data, P.shape[0], P.shape[1], C.byref(o), C.byref(h)),
            "mpm_build_wm")
+    ix = Index(h.value, ALGO_WM)
+    return ix.upload() if upload else ix
+
+
+def _var_patterns(patterns):
+    """Patterns of any lengths (a list of byte strings or uint8 arrays) as
+    one byte array and d + 1 offsets."""
+    pats = [bytes(np.asarray(p, np.uint8).tobytes()) if not isinstance(p, (bytes, bytearray))
+            else bytes(p) for p in patterns]
+    if not pats:
+        raise MpmError(MPM_EINVAL, "no patterns")
+    off = np.zeros(len(pats) + 1, np.uint64)
+    off[1:] = np.cumsum([len(p) for p in pats])
+    data = np.frombuffer(b"".join(pats) or b"\0", np.uint8).copy()
+    return data, off
+
+
+def build_ac_var(patterns, upload: bool = False) -> Index:
+    """Aho-Corasick index over patterns of different lengths (the automaton of
+    the reversed strings; equal lengths give build_ac's index)."""
+    data, off = _var_patterns(patterns)
+    h = C.c_void_p()
+    _check(_L.mpm_build_ac_var(data.ctypes.data, off.ctypes.data, len(off) - 1, None, C.byref(h)),
+           "mpm_build_ac_var")
+    ix = Index(h.value, ALGO_AC)
+    return ix.upload() if upload else ix
+
+
+def build_wm_var(patterns, B: int = 0, upload: bool = False) -> Index:
+    """Wu-Manber index over patterns of different lengths (window: the
+    shortest length; equal lengths give build_wm's index)."""
+    data, off = _var_patterns(patterns)
+    h = C.c_void_p()
+    o = Opts()
+    o.wm_block = B
+    _check(_L.mpm_build_wm_var(data.ctypes.data, off.ctypes.data, len(off) - 1, C.byref(o),
+                               C.byref(h)), "mpm_build_wm_var")
     ix = Index(h.value, ALGO_WM)
     return ix.upload() if upload else ix
 

@@ -43,6 +43,58 @@ static uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 // ---------------------------------------------------------------------------
 // Distinct pattern strings
 // ---------------------------------------------------------------------------
+// Number the distinct strings by their number of ids (ascending), each
+// group in ascending string order: strings u < n_single stand for exactly
+// one id, and within a group of strings with c ids the id list of u starts
+// at group_off + (u - group_start) * c, so the scan counts and finds a
+// string's ids without reading the CSR offsets.
+static mpm_status number_by_count(mpm_index *ix)
+{
+    const uint32_t m = ix->m;
+    auto str_begin = [&](uint32_t u) -> uint64_t { return ix->var ? ix->upoff[u] : (uint64_t)u * m; };
+    auto str_end = [&](uint32_t u) -> uint64_t { return ix->var ? ix->upoff[u + 1] : (uint64_t)(u + 1) * m; };
+    std::vector<uint32_t> perm(ix->du);
+    std::iota(perm.begin(), perm.end(), 0u);
+    std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) {
+        return ix->uoff[a + 1] - ix->uoff[a] < ix->uoff[b + 1] - ix->uoff[b];
+    });
+    ix->n_single = 0;
+    while (ix->n_single < ix->du &&
+           ix->uoff[perm[ix->n_single] + 1] - ix->uoff[perm[ix->n_single]] == 1)
+        ix->n_single++;
+    if (ix->n_single < ix->du) {
+        std::vector<uint32_t> uoff2(1, 0), uids2, upoff2(1, 0);
+        std::vector<uint8_t> upats2;
+        uids2.reserve(ix->uids.size());
+        upats2.reserve(ix->upats.size());
+        for (uint32_t u : perm) {
+            for (uint32_t j = ix->uoff[u]; j < ix->uoff[u + 1]; j++)
+                uids2.push_back(ix->uids[j]);
+            uoff2.push_back((uint32_t)uids2.size());
+            upats2.insert(upats2.end(), ix->upats.begin() + str_begin(u), ix->upats.begin() + str_end(u));
+            upoff2.push_back((uint32_t)upats2.size());
+        }
+        ix->uoff.swap(uoff2);
+        ix->uids.swap(uids2);
+        ix->upats.swap(upats2);
+        if (ix->var)
+            ix->upoff.swap(upoff2);
+    }
+    // groups of strings sharing an id count above one
+    ix->grp_u0.clear();
+    ix->grp_cnt.clear();
+    ix->grp_off.clear();
+    for (uint32_t u = ix->n_single; u < ix->du; u++) {
+        const uint32_t c = ix->uoff[u + 1] - ix->uoff[u];
+        if (ix->grp_cnt.empty() || ix->grp_cnt.back() != c) {
+            ix->grp_u0.push_back(u);
+            ix->grp_cnt.push_back(c);
+            ix->grp_off.push_back(ix->uoff[u]);
+        }
+    }
+    return MPM_OK;
+}
+
 // The Definition reports every pattern id, so equal patterns are kept as one
 // string with an ascending id list (the output set of a terminal state in
 // Algorithm 1 holds every pattern that ends there).
@@ -75,49 +127,80 @@ static mpm_status dedup(const uint8_t *P, uint32_t d, uint32_t m, mpm_index *ix)
     ix->max_dup = std::max(ix->max_dup, run);
     ix->uoff.push_back(d);
     ix->du = (uint32_t)(ix->uoff.size() - 1);
-    // Number the distinct strings by their number of ids (ascending), each
-    // group in ascending string order: strings u < n_single stand for exactly
-    // one id, and within a group of strings with c ids the id list of u starts
-    // at group_off + (u - group_start) * c, so the scan counts and finds a
-    // string's ids without reading the CSR offsets.
-    std::vector<uint32_t> perm(ix->du);
-    std::iota(perm.begin(), perm.end(), 0u);
-    std::stable_sort(perm.begin(), perm.end(), [&](uint32_t a, uint32_t b) {
-        return ix->uoff[a + 1] - ix->uoff[a] < ix->uoff[b + 1] - ix->uoff[b];
+    return number_by_count(ix);
+}
+
+// Patterns of different lengths (pattern r is P[off[r] .. off[r + 1])): the
+// Definition read with a length per pattern. Wherever a distinct string
+// occurs, so does every pattern that is a prefix of it, so each distinct
+// string keeps the ascending ids of all of them; a scan reports, per start,
+// only the longest distinct string found there. In sorted order a string's
+// prefixes in the set are the chain kept on a stack, and its list is its
+// longest proper prefix's list merged with its own ids.
+static mpm_status dedup_var(const uint8_t *P, const uint64_t *off, uint32_t d, mpm_index *ix)
+{
+    auto len = [&](uint32_t r) { return off[r + 1] - off[r]; };
+    auto cmp = [&](uint32_t a, uint32_t b) -> int {
+        const uint64_t la = len(a), lb = len(b);
+        const int c = memcmp(P + off[a], P + off[b], std::min(la, lb));
+        if (c)
+            return c;
+        return la < lb ? -1 : la > lb ? 1 : 0;  // a proper prefix sorts first
+    };
+    std::vector<uint32_t> order(d);
+    std::iota(order.begin(), order.end(), 0u);
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        const int c = cmp(a, b);
+        return c != 0 ? c < 0 : a < b;
     });
-    ix->n_single = 0;
-    while (ix->n_single < ix->du &&
-           ix->uoff[perm[ix->n_single] + 1] - ix->uoff[perm[ix->n_single]] == 1)
-        ix->n_single++;
-    if (ix->n_single < ix->du) {
-        std::vector<uint32_t> uoff2(1, 0), uids2;
-        std::vector<uint8_t> upats2;
-        uids2.reserve(d);
-        upats2.reserve(ix->upats.size());
-        for (uint32_t u : perm) {
-            for (uint32_t j = ix->uoff[u]; j < ix->uoff[u + 1]; j++)
-                uids2.push_back(ix->uids[j]);
-            uoff2.push_back((uint32_t)uids2.size());
-            upats2.insert(upats2.end(), ix->upats.begin() + (uint64_t)u * m,
-                          ix->upats.begin() + (uint64_t)(u + 1) * m);
+    // distinct strings and their own ids
+    std::vector<uint32_t> own_off, own_ids(d);
+    ix->upats.clear();
+    ix->upoff.assign(1, 0);
+    for (uint32_t k = 0; k < d; k++) {
+        const uint32_t r = order[k];
+        if (k == 0 || cmp(r, order[k - 1]) != 0) {
+            own_off.push_back(k);
+            if (ix->upats.size() + len(r) >= (1ull << 32))
+                return fail(MPM_ETOOBIG, "build: distinct pattern bytes exceed 4 GiB");
+            ix->upats.insert(ix->upats.end(), P + off[r], P + off[r + 1]);
+            ix->upoff.push_back((uint32_t)ix->upats.size());
         }
-        ix->uoff.swap(uoff2);
-        ix->uids.swap(uids2);
-        ix->upats.swap(upats2);
+        own_ids[k] = r;
     }
-    // groups of strings sharing an id count above one
-    ix->grp_u0.clear();
-    ix->grp_cnt.clear();
-    ix->grp_off.clear();
-    for (uint32_t u = ix->n_single; u < ix->du; u++) {
-        const uint32_t c = ix->uoff[u + 1] - ix->uoff[u];
-        if (ix->grp_cnt.empty() || ix->grp_cnt.back() != c) {
-            ix->grp_u0.push_back(u);
-            ix->grp_cnt.push_back(c);
-            ix->grp_off.push_back(ix->uoff[u]);
+    own_off.push_back(d);
+    ix->du = (uint32_t)(own_off.size() - 1);
+    auto is_prefix = [&](uint32_t v, uint32_t u) {  // distinct string v a prefix of u
+        const uint32_t lv = ix->upoff[v + 1] - ix->upoff[v], lu = ix->upoff[u + 1] - ix->upoff[u];
+        return lv <= lu && memcmp(ix->upats.data() + ix->upoff[v], ix->upats.data() + ix->upoff[u], lv) == 0;
+    };
+    ix->uoff.assign(1, 0);
+    ix->uids.clear();
+    ix->max_dup = 0;
+    std::vector<uint32_t> chain;
+    for (uint32_t u = 0; u < ix->du; u++) {
+        while (!chain.empty() && !is_prefix(chain.back(), u))
+            chain.pop_back();
+        const uint32_t *ob = own_ids.data() + own_off[u], *oe = own_ids.data() + own_off[u + 1];
+        std::sort(own_ids.begin() + own_off[u], own_ids.begin() + own_off[u + 1]);
+        const uint64_t base = ix->uids.size();
+        if (chain.empty()) {
+            ix->uids.insert(ix->uids.end(), ob, oe);
+        } else {
+            const uint32_t v = chain.back();
+            const uint64_t pb = ix->uoff[v], pe = ix->uoff[v + 1];
+            if (base + (pe - pb) + (oe - ob) >= (1ull << 31))
+                return fail(MPM_ETOOBIG, "build: id lists of prefix patterns exceed 2^31 entries");
+            ix->uids.resize(base + (pe - pb) + (oe - ob));
+            // the prefix's list lives in uids too: merge from a copy
+            std::vector<uint32_t> pre(ix->uids.begin() + pb, ix->uids.begin() + pe);
+            std::merge(pre.begin(), pre.end(), ob, oe, ix->uids.begin() + base);
         }
+        ix->uoff.push_back((uint32_t)ix->uids.size());
+        ix->max_dup = std::max<uint32_t>(ix->max_dup, (uint32_t)(ix->uids.size() - base));
+        chain.push_back(u);
     }
-    return MPM_OK;
+    return number_by_count(ix);
 }
 
 template <typename T>
@@ -359,6 +442,13 @@ static inline uint32_t wm_block_hash(const uint8_t *p, uint32_t B, uint32_t sh)
     return h;
 }
 
+// The first m bytes of every distinct string, m bytes each: the strings
+// themselves for one length, their window prefixes for several.
+static const uint8_t *wm_windows(const mpm_index *ix)
+{
+    return ix->var ? ix->wpats.data() : ix->upats.data();
+}
+
 static void wm_tables(const mpm_index *ix, uint32_t B, uint32_t sh, std::vector<uint8_t> &shift,
                       std::vector<uint32_t> &bcount)
 {
@@ -366,8 +456,9 @@ static void wm_tables(const mpm_index *ix, uint32_t B, uint32_t sh, std::vector<
     const uint32_t H = 1u << (2 * B);
     shift.assign(H, (uint8_t)(m - B + 1));
     bcount.assign(H, 0);
+    const uint8_t *win = wm_windows(ix);
     for (uint32_t u = 0; u < ix->du; u++) {
-        const uint8_t *p = ix->upats.data() + (uint64_t)u * m;
+        const uint8_t *p = win + (uint64_t)u * m;
         for (uint32_t q = B; q <= m; q++) {
             // the block p_{q-B} .. p_{q-1}, m - q characters from the end
             uint32_t h = wm_block_hash(p + q - B, B, sh);
@@ -406,8 +497,9 @@ static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
     // pattern characters with that code), so frequent bytes get codes of
     // their own.
     double freq[256] = {0};
-    for (uint8_t b : ix->upats)
-        freq[b] += 1.0;
+    const uint8_t *win = wm_windows(ix);
+    for (uint64_t k = 0; k < (uint64_t)ix->du * m; k++)
+        freq[win[k]] += 1.0;
     uint32_t best_sh = 0;
     double best_c = 1e300;
     for (uint32_t sh = 0; sh < 6; sh++) {
@@ -470,8 +562,17 @@ static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
     ix->bu.assign(ix->du, 0);
     ix->bkey.assign(ix->du, 0);
     std::vector<uint32_t> fillp(ix->boff.begin(), ix->boff.end() - 1);
-    for (uint32_t u = 0; u < ix->du; u++) {  // ascending ranks within a bucket
-        const uint8_t *p = ix->upats.data() + (uint64_t)u * m;
+    // Ascending ranks within a bucket; for several lengths, longer strings
+    // first, so that the first string found at a window is the longest one
+    // starting there.
+    std::vector<uint32_t> fill_order(ix->du);
+    std::iota(fill_order.begin(), fill_order.end(), 0u);
+    if (ix->var)
+        std::stable_sort(fill_order.begin(), fill_order.end(), [&](uint32_t a, uint32_t b) {
+            return ix->upoff[a + 1] - ix->upoff[a] > ix->upoff[b + 1] - ix->upoff[b];
+        });
+    for (uint32_t u : fill_order) {
+        const uint8_t *p = win + (uint64_t)u * m;
         uint32_t h = wm_block_hash(p + m - B, B, best_sh);
         uint32_t slot = fillp[bucket_of[h]]++;
         ix->bu[slot] = u;
@@ -499,6 +600,8 @@ static mpm_status build_wm_tables(mpm_index *ix, uint32_t B_req)
     ix->off_e = put(ix->image, ix->upats.data(), ix->upats.size());
     ix->off_f = put(ix->image, ix->uoff.data(), ix->uoff.size());
     ix->off_g = put(ix->image, ix->uids.data(), ix->uids.size());
+    if (ix->var)
+        ix->off_h = put(ix->image, ix->upoff.data(), ix->upoff.size());
     ix->image.resize(align_up(ix->image.size(), 256), 0);
     return MPM_OK;
 }
@@ -583,6 +686,105 @@ mpm_status mpm_build_wm(const uint8_t *patterns, uint32_t d, uint32_t m, const m
     }
 }
 
+// Sets of different lengths: checks, and the lengths (0: offsets invalid).
+static mpm_status var_args(const uint8_t *bytes, const uint64_t *off, uint32_t d, mpm_index **out,
+                           uint32_t *m_min, uint32_t *m_max, const char *who)
+{
+    if (!out)
+        return fail(MPM_EINVAL, "%s: out is NULL", who);
+    *out = nullptr;
+    if (!bytes || !off)
+        return fail(MPM_EINVAL, "%s: patterns or offsets is NULL", who);
+    if (d == 0)
+        return fail(MPM_EINVAL, "%s: d must be positive", who);
+    uint64_t lo = ~0ull, hi = 0;
+    for (uint32_t r = 0; r < d; r++) {
+        if (off[r + 1] <= off[r])
+            return fail(MPM_EINVAL, "%s: pattern %u is empty or its offsets descend", who, r);
+        lo = std::min(lo, off[r + 1] - off[r]);
+        hi = std::max(hi, off[r + 1] - off[r]);
+    }
+    if (off[d] - off[0] > (1ull << 34))
+        return fail(MPM_ETOOBIG, "%s: pattern bytes exceed 16 GiB", who);
+    if (hi >= (1ull << 31))
+        return fail(MPM_ETOOBIG, "%s: a pattern of %llu bytes", who, (unsigned long long)hi);
+    *m_min = (uint32_t)lo;
+    *m_max = (uint32_t)hi;
+    return MPM_OK;
+}
+
+mpm_status mpm_build_ac_var(const uint8_t *patterns, const uint64_t *offsets, uint32_t d,
+                            const mpm_opts *opts, mpm_index **out)
+{
+    uint32_t lo = 0, hi = 0;
+    mpm_status st = var_args(patterns, offsets, d, out, &lo, &hi, "mpm_build_ac_var");
+    if (st)
+        return st;
+    if (lo == hi)  // one length: rows are contiguous
+        return mpm_build_ac(patterns + offsets[0], d, lo, opts, out);
+    if (opts && opts->ac_goto)
+        return fail(MPM_EUNSUPPORTED, "mpm_build_ac_var: the supply-link walk needs one length");
+    try {
+        mpm_index *ix = new mpm_index();
+        ix->algo = MPM_ALGO_AC;
+        ix->var = 1;
+        ix->m = lo;
+        ix->m_max = hi;
+        ix->d = d;
+        st = dedup_var(patterns, offsets, d, ix);
+        if (!st)
+            st = build_ac_rev_tables(ix);
+        if (st) {
+            delete ix;
+            return st;
+        }
+        *out = ix;
+        g_err.clear();
+        return MPM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPM_ENOMEM, "mpm_build_ac_var: out of host memory");
+    }
+}
+
+mpm_status mpm_build_wm_var(const uint8_t *patterns, const uint64_t *offsets, uint32_t d,
+                            const mpm_opts *opts, mpm_index **out)
+{
+    uint32_t lo = 0, hi = 0;
+    mpm_status st = var_args(patterns, offsets, d, out, &lo, &hi, "mpm_build_wm_var");
+    if (st)
+        return st;
+    if (lo == hi)
+        return mpm_build_wm(patterns + offsets[0], d, lo, opts, out);
+    const uint32_t B = opts ? opts->wm_block : 0;
+    if (B != 0 && (B > lo || B > 8))
+        return fail(MPM_EUNSUPPORTED, "mpm_build_wm_var: B=%u needs 1 <= B <= min(shortest "
+                    "length %u, 8)", B, lo);
+    try {
+        mpm_index *ix = new mpm_index();
+        ix->algo = MPM_ALGO_WM;
+        ix->var = 1;
+        ix->m = lo;
+        ix->m_max = hi;
+        ix->d = d;
+        st = dedup_var(patterns, offsets, d, ix);
+        if (!st) {
+            ix->wpats.resize((uint64_t)ix->du * lo);
+            for (uint32_t u = 0; u < ix->du; u++)
+                memcpy(ix->wpats.data() + (uint64_t)u * lo, ix->upats.data() + ix->upoff[u], lo);
+            st = build_wm_tables(ix, B);
+        }
+        if (st) {
+            delete ix;
+            return st;
+        }
+        *out = ix;
+        g_err.clear();
+        return MPM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(MPM_ENOMEM, "mpm_build_wm_var: out of host memory");
+    }
+}
+
 void mpm_free(mpm_index *idx) { delete idx; }
 
 uint64_t mpm_device_bytes(const mpm_index *idx) { return idx ? idx->image.size() : 0; }
@@ -627,6 +829,7 @@ mpm_status mpm_index_info(const mpm_index *idx, mpm_info *o)
     o->wm_mean_shift = idx->mean_shift;
     o->table_bytes = idx->table_bytes;
     o->device_bytes = idx->image.size();
+    o->m_max = idx->var ? idx->m_max : idx->m;
     return MPM_OK;
 }
 
@@ -920,6 +1123,11 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
                 delete b;
                 return fail(MPM_ESTATE, "mpm_batch_plan: request %u: index not uploaded", k);
             }
+            if (r.idx->var) {
+                delete b;
+                return fail(MPM_EUNSUPPORTED, "mpm_batch_plan: request %u: sets of different "
+                            "lengths run in single-text scans only", k);
+            }
             if (r.n >= (1ull << 32)) {
                 delete b;
                 return fail(MPM_ETOOBIG, "mpm_batch_plan: request %u: n >= 2^32", k);
@@ -1056,6 +1264,9 @@ mpm_status mpm_batch_launch_key(const mpm_index *idx, const mpm_variant *variant
 {
     if (!idx || !key)
         return fail(MPM_EINVAL, "mpm_batch_launch_key: null argument");
+    if (idx->var)
+        return fail(MPM_EUNSUPPORTED, "mpm_batch_launch_key: sets of different lengths run in "
+                    "single-text scans only");
     mpm_variant v = variant ? *variant : mpm_variant{0, 0, 0, 0, 0};
     v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
     LaunchCfg cfg;
@@ -1217,6 +1428,9 @@ static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
 {
     if (!idx || copies == 0)
         return fail(MPM_EINVAL, "mpm_tune: null index or zero copies");
+    if (idx->var)
+        return fail(MPM_EUNSUPPORTED, "mpm_tune: sets of different lengths run in single-text "
+                    "scans only");
     mpm_variant w = v ? *v : mpm_variant{0, 0, 0, 0, 0};
     w.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
     mpm_status st = resolve_variant(idx, &w, 0, cfg);

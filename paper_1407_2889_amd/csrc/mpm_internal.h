@@ -68,6 +68,11 @@ struct AcDev {
     uint32_t swar_ok;
     uint32_t swar_shift;
     uint32_t perm_byte_lo, perm_byte_hi, perm_col_lo, perm_col_hi;
+    // Sets of different lengths: the table is the automaton of the reversed
+    // strings, walked from a range's end to its start; a state s >=
+    // first_term reports string term_u[s - first_term] (null for one length).
+    const uint32_t *term_u;
+    uint32_t m_max;         // longest string (m: the shortest)
 };
 
 // Wu-Manber tables. Characters map to 2-bit codes (c >> code_shift) & 3; a
@@ -92,6 +97,11 @@ struct WmDev {
     uint32_t n_single;
     uint32_t shift_bytes;   // bytes of SHIFT at the start of `tables` (multiple of 16)
     IdGroups grp;
+    // Sets of different lengths (var != 0): m is the shortest length, the
+    // window; string u is pats[upoff[u] .. upoff[u + 1]) and buckets list
+    // longer strings first. Null for one length.
+    const uint32_t *upoff;
+    uint32_t var;
 };
 
 // One text of a launch. Tiles of a launch are numbered globally; a text
@@ -203,6 +213,13 @@ struct mpm_index {
     // its first string's ids start at grp_off[k].
     std::vector<uint32_t> grp_u0, grp_cnt, grp_off;
     std::vector<uint8_t> upats;         // du * m, ascending strings
+    // Sets of different lengths (var): m is the shortest length, m_max the
+    // longest; string u is upats[upoff[u] .. upoff[u + 1]) and its id list
+    // holds the ids of every pattern that is a prefix of it (those occur
+    // wherever it does).
+    uint32_t var = 0, m_max = 0;
+    std::vector<uint32_t> upoff;
+    std::vector<uint8_t> wpats;         // Wu-Manber: first m bytes of every string
 
     // Aho-Corasick
     uint32_t n_classes = 0;
@@ -213,6 +230,8 @@ struct mpm_index {
     uint64_t n_states = 0;
     uint32_t state_bytes = 0;
     std::vector<uint32_t> dfa;          // n_states * (1 + n_classes)
+    uint64_t first_term = 0;            // var: states from here on report a string
+    std::vector<uint32_t> term_u;       // var: the string each reporting state reports
 
     // Wu-Manber
     uint32_t B = 0, code_shift = 0, zero_shift = 0, n_buckets = 0, key_len = 0;
@@ -223,7 +242,7 @@ struct mpm_index {
 
     // Device image: host copy, offsets, and the caller-owned device buffer.
     std::vector<uint8_t> image;
-    uint64_t off_a = 0, off_b = 0, off_c = 0, off_d = 0, off_e = 0, off_f = 0, off_g = 0;
+    uint64_t off_a = 0, off_b = 0, off_c = 0, off_d = 0, off_e = 0, off_f = 0, off_g = 0, off_h = 0;
     // Aho-Corasick goto rows and supply links (kept when asked for)
     uint32_t keep_goto = 0;
     uint64_t off_go = 0, go_bytes = 0, sup_off = 0;
@@ -268,6 +287,10 @@ mpm_status launch_zero_totals(uint64_t *const *d_totals_dev, uint32_t count, uin
 // Aho-Corasick table shrinks by as much).
 AcDev ac_dev(const mpm_index *ix, uint32_t reserve = 0);
 WmDev wm_dev(const mpm_index *ix);
+// Sets of different lengths (mpm_mixed.cpp, mpm_scan_var.hip).
+mpm_status build_ac_rev_tables(mpm_index *ix);
+const void *var_kernel(const mpm_index *ix, const LaunchCfg &c);
+mpm_status var_launch(const mpm_index *ix, const LaunchCfg &c, const ScanDev &sd, void *stream);
 uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c);
 // Batched launches run one kernel per walker kind (BK_*, with BK_SWAR).
 uint32_t batch_grid(uint32_t kind, uint32_t W, uint32_t lds_bytes, uint64_t ntiles,

@@ -131,6 +131,10 @@ AcDev ac_dev(const mpm_index *ix, uint32_t reserve)
     a.go_bytes = (uint32_t)ix->go_bytes;
     a.sup_off = (uint32_t)ix->sup_off;
     a.hot_states = (uint32_t)(hb / ((uint64_t)a.cp * ix->state_bytes));
+    a.term_u = ix->var ? (const uint32_t *)(ix->d_image + ix->off_e) : nullptr;
+    a.m_max = ix->var ? ix->m_max : ix->m;
+    if (ix->var)
+        a.first_term = (uint32_t)ix->first_term;
     return a;
 }
 
@@ -153,13 +157,17 @@ WmDev wm_dev(const mpm_index *ix)
     a.n_single = ix->n_single;
     a.grp = id_groups(ix);
     a.shift_bytes = (uint32_t)(((uint64_t)ix->shift16.size() * 2 + 15) / 16 * 16);
+    a.upoff = ix->var ? (const uint32_t *)(ix->d_image + ix->off_h) : nullptr;
+    a.var = ix->var;
     return a;
 }
 
 // Whether an index can run with the hot part of its tables in LDS.
 static bool has_hot(const mpm_index *ix)
 {
-    return ix->algo == MPM_ALGO_WM || ix->algo == MPM_ALGO_AC;
+    // the reversed walk of sets of different lengths reads the whole table
+    // from one place
+    return ix->algo == MPM_ALGO_WM || (ix->algo == MPM_ALGO_AC && !ix->var);
 }
 
 // LDS bytes of the hot part (reserve: bytes the launch keeps beside it).
@@ -172,6 +180,8 @@ static uint64_t hot_lds_bytes(const mpm_index *ix, uint32_t reserve)
 
 static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
 {
+    if (ix->var)
+        return var_kernel(ix, c);
     if (ix->algo == MPM_ALGO_AC && c.supply)
         return ac_supply_kernel(ix->state_bytes, c);
     if (ix->algo == MPM_ALGO_AC) {
@@ -190,7 +200,7 @@ uint64_t tile_bytes(const LaunchCfg &cfg)
 }
 
 uint32_t csr_uoff_words(const mpm_index *ix) { return (ix->du + 1 + 3) / 4 * 4; }
-uint32_t csr_uids_words(const mpm_index *ix) { return (ix->d + 3) / 4 * 4; }
+uint32_t csr_uids_words(const mpm_index *ix) { return ((uint32_t)ix->uids.size() + 3) / 4 * 4; }
 
 mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t ntiles,
                            LaunchCfg *cfg, bool csr_in_lds)
@@ -212,6 +222,9 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     if (dense && (d.flags & (MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY)))
         return fail(MPM_EUNSUPPORTED, "variant: dense output runs the flattened walk, one range "
                     "per lane");
+    if (ix->var && (d.flags & (MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY | MPM_VARIANT_DENSE)))
+        return fail(MPM_EUNSUPPORTED, "variant: sets of different lengths run one range per lane "
+                    "with the flattened walk and per-lane output");
     if (dense && d.block_threads && d.block_threads != 1024)
         return fail(MPM_EINVAL, "variant: dense output needs block_threads 1024");
     if (dense) {
@@ -298,6 +311,8 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
     if (c.lds_bytes > 65536)
         (void)hipFuncSetAttribute(kernel_for(ix, c), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)c.lds_bytes);
+    if (ix->var)
+        return var_launch(ix, c, sd, stream);
     if (ix->algo == MPM_ALGO_AC && c.supply) {
         e = ac_supply_launch(ix->state_bytes, ac_dev(ix), c, sd, s);
     } else if (ix->algo == MPM_ALGO_AC) {

@@ -449,6 +449,7 @@ template <typename St, int P, bool Swar, int Ilp>
 struct AcWalk {
     using Dev = AcDev;
     static constexpr int ILP = Ilp;
+    static constexpr bool DESC = false;  // reports starts in ascending order
     static constexpr bool InLds = P == PL_LDS;
     // PL_HOT: states below hot (the first rows in breadth-first order, where
     // a walk over text spends nearly all its steps) are read from LDS, the
@@ -974,6 +975,7 @@ template <typename St, int P>
 struct AcSupplyWalk {
     using Dev = AcDev;
     static constexpr int ILP = 1;
+    static constexpr bool DESC = false;
     static constexpr bool InLds = P == PL_LDS;
     static constexpr uint32_t FAIL = sizeof(St) == 2 ? 0xffffu : 0xffffffffu;
     typename TabPtr<InLds, uint8_t>::type gob;  // goto rows, addressed in bytes
@@ -1058,6 +1060,130 @@ struct AcSupplyWalk {
 };
 
 // ---------------------------------------------------------------------------
+// Aho-Corasick over the reversed strings (sets of different lengths)
+// ---------------------------------------------------------------------------
+// Bytes [a, e) of a text from e - 1 down to a: single bytes down to a 16-byte
+// boundary, 16-byte pieces, then single bytes. one(byte, pos) and
+// sixteen(v4u, pos of its first byte) consume; a piece's bytes are taken
+// from its last to its first.
+template <class F1, class F16>
+__device__ __forceinline__ void rstream_text(glb_cptr<uint8_t> text, uint64_t a, uint64_t e,
+                                             F1 &&one, F16 &&sixteen)
+{
+    uint64_t p = e;
+    while (p > a && (((uintptr_t)(text + p)) & 15u)) {
+        --p;
+        one((uint32_t)text[p], p);
+    }
+    while (p >= a + 16) {
+        p -= 16;
+        sixteen(*(glb_cptr<v4u>)(text + p), p);
+    }
+    while (p > a) {
+        --p;
+        one((uint32_t)text[p], p);
+    }
+}
+
+// A lane walks its range backwards with the automaton of the reversed
+// strings. After the byte at q, the state's label is the longest string
+// that starts at q and ends some string of the set; the state reports a
+// string exactly when one starts at q, namely the longest one, whose id list
+// holds every pattern that is a prefix of it (Section 3.1's output sets,
+// merged along the supply links of the reversed automaton). The state at q
+// depends on the bytes [q, q + m_max) only, so a lane starts m_max - 1 bytes
+// past its range. Starts are reported in descending order.
+template <typename St, int P>
+struct AcRevWalk {
+    using Dev = AcDev;
+    static constexpr int ILP = 1;
+    static constexpr bool DESC = true;
+    static constexpr bool InLds = P == PL_LDS;
+    typename TabPtr<InLds, uint8_t>::type dfab;  // table, addressed in bytes
+    lds_cptr<uint16_t> cls;                      // column byte offset per byte value
+    glb_cptr<uint32_t> term;                     // string of each reporting state
+    uint32_t rowb, first_term, mx;
+
+    template <int W>
+    __device__ __forceinline__ static void load(const AcDev &a)
+    {
+        copy_to_lds<W>(LDS_CLS_OFF, a.cls, 512);
+        if (InLds)
+            copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.dfa_bytes);
+    }
+
+    __device__ __forceinline__ void bind(const AcDev &a)
+    {
+        rowb = a.cp * (uint32_t)sizeof(St);
+        first_term = a.first_term;
+        mx = a.m_max;
+        cls = lds_at<const uint16_t>(LDS_CLS_OFF);
+        if constexpr (InLds)
+            dfab = lds_at<const uint8_t>(LDS_TAB_OFF);
+        else
+            dfab = (glb_cptr<uint8_t>)a.dfa;
+        term = (glb_cptr<uint32_t>)a.term_u;
+    }
+
+    template <int W>
+    __device__ __forceinline__ void setup(const AcDev &a, uint32_t /*unused*/)
+    {
+        load<W>(a);
+        bind(a);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ uint32_t next(uint32_t s, uint32_t coloff) const
+    {
+        const uint32_t off = sizeof(St) == 2 ? __umul24(s, rowb) + coloff : s * rowb + coloff;
+        return *(typename TabPtr<InLds, St>::type)(dfab + off);
+    }
+
+    // Starts [base + lo, base + hi), from the last to the first.
+    template <class F>
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        if (lo >= hi)
+            return;
+        const uint64_t a = base + lo, b = base + hi;
+        uint64_t e = b + mx - 1;
+        if (e > n)
+            e = n;
+        uint32_t s = 0;
+        auto one = [&](uint32_t byte, uint64_t q) {
+            s = next(s, cls[byte]);
+            if (s >= first_term && q < b)
+                cb(q, term[s - first_term]);
+        };
+        rstream_text(text, a, e, one, [&](const v4u c, uint64_t q) {
+            const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+            uint32_t st[16];
+            uint32_t mxs = 0;
+#pragma unroll
+            for (int j = 15; j >= 0; --j) {
+                s = next(s, cls[(w[j >> 2] >> (8 * (j & 3))) & 0xffu]);
+                st[j] = s;
+                mxs = max(mxs, s);
+            }
+            if (mxs >= first_term) {
+#pragma unroll
+                for (int j = 15; j >= 0; --j)
+                    if (st[j] >= first_term && q + j < b)
+                        cb(q + j, term[st[j] - first_term]);
+            }
+        });
+    }
+
+    template <class F>
+    __device__ __forceinline__ void lane_again(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                               uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        lane(text, n, base, lo, hi, cb);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Wu-Manber walker
 // ---------------------------------------------------------------------------
 static const int WM_QUEUE = 4;  // filtered candidates kept before exact checks
@@ -1070,10 +1196,14 @@ __device__ __forceinline__ uint32_t codes4(uint32_t w, uint32_t sh)
     return (x | (x >> 12)) & 0xFFu;
 }
 
-template <int P>
+// Var: strings of different lengths (the window is the shortest length; a
+// bucket lists longer strings first and the first one that matches a window
+// is the one reported there, its id list covering the shorter matches).
+template <int P, bool Var = false>
 struct WmWalk {
     using Dev = WmDev;
     static constexpr int ILP = 1;
+    static constexpr bool DESC = false;
     static constexpr bool InLds = P == PL_LDS;
     // PL_HOT: SHIFT (read for every window) in LDS, the buckets (read only
     // for windows with a zero shift) in global memory.
@@ -1081,6 +1211,7 @@ struct WmWalk {
     typename TabPtr<InLds || Hot, uint16_t>::type sh16;
     typename TabPtr<InLds, uint32_t>::type boff, bkey, bu;
     glb_cptr<uint8_t> pats;
+    glb_cptr<uint32_t> upoff;  // Var: string u is pats[upoff[u] .. upoff[u + 1])
     uint32_t m, B, csh, kl, hmask, kmask;
 
     // Copy what this walker reads from LDS (no barrier).
@@ -1114,6 +1245,7 @@ struct WmWalk {
         bkey = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bkey);
         bu = (typename TabPtr<InLds, uint32_t>::type)(base + a.off_bu);
         pats = (glb_cptr<uint8_t>)a.pats;
+        upoff = (glb_cptr<uint32_t>)a.upoff;
     }
 
     template <int W>
@@ -1161,21 +1293,43 @@ struct WmWalk {
         // Exact check of the queued candidates, eight bytes of window and
         // pattern per step with no early exit, so a step's loads are in
         // flight together.
+        // Var: window end of the last report (a window reports one string).
+        uint32_t done = 0xffffffffu;
         auto flush = [&]() {
 #pragma unroll
             for (int k = 0; k < WM_QUEUE; ++k) {
                 if ((uint32_t)k < qn) {
                     const uint64_t st = (uint64_t)qp[k] + 1 - m;
-                    glb_cptr<uint8_t> pp = pats + (uint64_t)qu[k] * m;
-                    uint32_t diff = 0;
-                    for (uint32_t j = 0; j < m; j += 8) {
+                    if constexpr (Var) {
+                        const uint32_t po = upoff[qu[k]];
+                        const uint32_t len = upoff[qu[k] + 1] - po;
+                        // strings running past the text's end do not occur
+                        if (qp[k] != done && st + len <= n) {
+                            glb_cptr<uint8_t> pp = pats + po;
+                            uint32_t diff = 0;
+                            for (uint32_t j = 0; j < len; j += 8) {
 #pragma unroll
-                        for (uint32_t t = 0; t < 8; ++t)
-                            if (j + t < m)
-                                diff |= (uint32_t)(pp[j + t] ^ text[st + j + t]);
+                                for (uint32_t t = 0; t < 8; ++t)
+                                    if (j + t < len)
+                                        diff |= (uint32_t)(pp[j + t] ^ text[st + j + t]);
+                            }
+                            if (diff == 0) {
+                                cb(st, qu[k]);
+                                done = qp[k];
+                            }
+                        }
+                    } else {
+                        glb_cptr<uint8_t> pp = pats + (uint64_t)qu[k] * m;
+                        uint32_t diff = 0;
+                        for (uint32_t j = 0; j < m; j += 8) {
+#pragma unroll
+                            for (uint32_t t = 0; t < 8; ++t)
+                                if (j + t < m)
+                                    diff |= (uint32_t)(pp[j + t] ^ text[st + j + t]);
+                        }
+                        if (diff == 0)
+                            cb(st, qu[k]);
                     }
-                    if (diff == 0)
-                        cb(st, qu[k]);
                 }
             }
             qn = 0;
@@ -1330,6 +1484,36 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
         // (a counting call with capacity 0 walks each range once)
         if (nu[v] == 0 || ob[v] >= cap)
             continue;
+        if constexpr (Walk::DESC) {
+            // Occurrences come from the range's last start down: each one's
+            // ids go just below the previous one's, from the lane's end.
+            uint64_t o = ob[v] + nid[v];
+            auto put = [&](uint32_t pos, uint32_t u) {
+                o -= im.count(u);
+                uint64_t w = o;
+                write_ids(out, cap, w, pos, u, im);
+            };
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                if ((uint32_t)k < nu[v])
+                    put(so[v][k], su[v][k]);
+            if (nu[v] > (uint32_t)KS) {
+                const uint32_t ns_ = min(nu[v] - (uint32_t)KS, scap);
+                for (uint32_t j = 0; j < ns_; ++j) {
+                    const v2u e = stg.base[(uint64_t)j * stg.lanes + threadIdx.x + v * W];
+                    put(e.x, e.y);
+                }
+            }
+            if (nu[v] > (uint32_t)KS + scap && o > ob[v]) {
+                // the rest start below the last kept or staged one
+                const uint32_t last =
+                    scap ? stg.base[(uint64_t)(scap - 1) * stg.lanes + threadIdx.x + v * W].x
+                         : so[v][KS - 1];
+                wk.lane_again(text, n, base, lo[v], (uint32_t)((uint64_t)last - base),
+                              [&](uint64_t start, uint32_t u) { put((uint32_t)start, u); });
+            }
+            continue;
+        }
         uint64_t o = ob[v];
 #pragma unroll
         for (int k = 0; k < KS; ++k)

@@ -56,6 +56,9 @@ extern "C" mpm_status mpm_scan_host(const mpm_index *idx, const uint8_t *h_text,
     if (!idx || !total || !d_total || !d_work || !d_stage || chunk == 0 || (n && !h_text) ||
         (capacity && !d_out))
         return fail(MPM_EINVAL, "mpm_scan_host: null argument or zero chunk");
+    if (idx->var)
+        return fail(MPM_EUNSUPPORTED, "mpm_scan_host: sets of different lengths need the whole "
+                    "text on the device");
     if (n >= (1ull << 32))
         return fail(MPM_ETOOBIG, "mpm_scan_host: n = %llu needs 32-bit positions",
                     (unsigned long long)n);

@@ -121,6 +121,40 @@ def pattern_set(text: np.ndarray, d: int, m: int, n_planted: int, seed: int,
     return ps
 
 
+def mixed_pattern_set(text: np.ndarray, d: int, lo: int, hi: int, n_planted: int, seed: int,
+                      n_prefix: int = 0, n_suffix: int = 0, n_dup: int = 0) -> list:
+    """d patterns (bytes) of lengths drawn uniformly from [lo, hi]: n_planted
+    newline-free text windows, then n_prefix leading parts and n_suffix
+    trailing parts (at least lo long) of planted ones, n_dup copies of planted
+    ones, and uniform ACGT strings for the rest, in a seeded shuffled order."""
+    rng = np.random.default_rng(seed)
+    pats = []
+    for _ in range(n_planted):
+        m = int(rng.integers(lo, hi + 1))
+        for _ in range(10000):
+            s = int(rng.integers(0, len(text) - m + 1))
+            w = text[s:s + m]
+            if not (w == NEWLINE).any():
+                break
+        else:
+            raise ValueError("could not plant a newline-free window")
+        pats.append(w.tobytes())
+    base = list(pats)
+    for _ in range(n_prefix):
+        p = base[int(rng.integers(0, len(base)))]
+        pats.append(p[:int(rng.integers(lo, len(p) + 1))])
+    for _ in range(n_suffix):
+        p = base[int(rng.integers(0, len(base)))]
+        pats.append(p[len(p) - int(rng.integers(lo, len(p) + 1)):])
+    for _ in range(n_dup):
+        pats.append(base[int(rng.integers(0, len(base)))])
+    while len(pats) < d:
+        m = int(rng.integers(lo, hi + 1))
+        pats.append(ACGT[rng.integers(0, 4, m)].tobytes())
+    order = rng.permutation(len(pats))
+    return [pats[i] for i in order[:d]]
+
+
 # ---------------------------------------------------------------------------
 # Named workloads. Sizes follow the paper's problem shape (Section 5: a 1 GiB
 # DNA string, m = 8, d in the thousands) scaled to the cases used here.
