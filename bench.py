@@ -344,29 +344,55 @@ def run_stream(args):
 
 
 def run_ablation(args):
-    """What the flattened table and its placement buy on the 256 MiB EST
-    text (d=1000, m=16): the goto function with supply links followed at run
-    time (the paper's kernel design, Section 4.2) against the flattened
-    table, each with the tables in global memory and, for the flattened
-    table, in LDS with and without register byte classes. Kernel time from
-    HIP events, the same lane ranges and workgroup size for every row; every
-    row's list is checked against the first. One JSON line."""
+    """The paper's kernel ladder (Section 4.2.2: unoptimised, texture-cached
+    tables, coalesced reads into shared memory, 16-byte reads, coalesced
+    writes) rebuilt for gfx950 on the 256 MiB EST text (d=1000, m=16): text
+    read a byte at a time from global memory, with the tables in global
+    memory then in LDS; the chunk's text staged in LDS by coalesced 16-byte
+    loads; 16-byte line streaming through registers (byte-class table, then
+    register byte classes); the benchmark's launch shape; then the other
+    table placements and the goto function with supply links. Writes: the
+    same scan counting only, writing the ordered list lane by lane, and
+    writing it in dense mode, on a dense set (d=100k, m=8). Kernel time from
+    HIP events; every row's list is checked against its group's first. One
+    JSON line."""
     import torch
     import paper_1407_2889_amd as mpm
+    import synth
     text, ps, desc = workload("est256")
     n = len(text)
     dev = torch.from_numpy(text).cuda()
     stream = torch.cuda.current_stream()
     ix = mpm.build_ac(ps.patterns, upload=True, goto=True)
     L, W = DEFAULT_VARIANTS["ac"]["lane_bytes"], DEFAULT_VARIANTS["ac"]["block_threads"]
-    rows_spec = [("flattened, LDS, register byte classes", mpm.PLACE_LDS, 0),
-                 ("flattened, LDS, byte-class table", mpm.PLACE_LDS, mpm.VARIANT_NO_SWAR),
-                 ("flattened, hot rows in LDS", mpm.PLACE_HOT, 0),
-                 ("flattened, global", mpm.PLACE_GLOBAL, 0),
-                 ("goto + supply links, global", mpm.PLACE_GLOBAL, mpm.VARIANT_SUPPLY)]
+    # Two launch shapes, both 1024 threads per workgroup: the benchmark's
+    # 1 KiB lanes (a 1 MiB chunk, too large to stage in LDS), and 16-byte
+    # lanes (a 16 KiB chunk, the largest whose text fits in LDS beside the
+    # 142 KB table) for the staged-text rung.
+    TB, TL, NS = mpm.VARIANT_TEXT_BYTES, mpm.VARIANT_TEXT_LDS, mpm.VARIANT_NO_SWAR
+    rows_spec = [
+        ("U: bytes one at a time from global memory, tables in global memory", L, W,
+         mpm.PLACE_GLOBAL, TB),
+        ("TC: tables in LDS (the paper's texture-cached tables), bytes from global memory", L, W,
+         mpm.PLACE_LDS, TB),
+        ("R16: 16-byte loads into registers, whole lines, byte-class table in LDS", L, W,
+         mpm.PLACE_LDS, NS),
+        ("R16 + register byte classes (the benchmark kernel)", L, W, mpm.PLACE_LDS, 0),
+        ("16-byte lanes, U: bytes from global memory, tables in global memory", 16, W,
+         mpm.PLACE_GLOBAL, TB),
+        ("16-byte lanes, TC: tables in LDS, bytes from global memory", 16, W, mpm.PLACE_LDS, TB),
+        ("16-byte lanes, CR: chunk text staged in LDS by coalesced 16-byte loads", 16, W,
+         mpm.PLACE_LDS, TL),
+        ("16-byte lanes, R16: 16-byte loads into registers, byte-class table", 16, W,
+         mpm.PLACE_LDS, NS),
+        ("16-byte lanes, R16 + register byte classes", 16, W, mpm.PLACE_LDS, 0),
+        ("benchmark launch shape, hot rows in LDS", L, W, mpm.PLACE_HOT, 0),
+        ("benchmark launch shape, tables in global memory", L, W, mpm.PLACE_GLOBAL, 0),
+        ("goto + supply links (not flattened), tables in global memory", L, W, mpm.PLACE_GLOBAL,
+         mpm.VARIANT_SUPPLY)]
     rows, ref = [], None
-    for name, pl, fl in rows_spec:
-        v = mpm.variant(lane_bytes=L, block_threads=W, placement=pl, flags=fl)
+    for name, l, w, pl, fl in rows_spec:
+        v = mpm.variant(lane_bytes=l, block_threads=w, placement=pl, flags=fl)
         sc = mpm.Scanner(ix, n, capacity=1 << 20, var=v)
         got = sc.scan(dev)
         if ref is None:
@@ -374,14 +400,103 @@ def run_ablation(args):
         elif not torch.equal(got, ref):
             raise SystemExit(f"ablation row '{name}' reports a different list")
         kms = time_scans(sc, dev, args.steps, args.warmup, stream)
-        rows.append({"kernel": name, "kernel_ms": round(kms, 4), "gbps": round(n / (kms * 1e-3) / 1e9, 2)})
+        rows.append({"kernel": name, "lane_bytes": l, "block_threads": w, "kernel_ms": round(kms, 4),
+                     "gbps": round(n / (kms * 1e-3) / 1e9, 2)})
         log(f"[bench] ablation {name}: {rows[-1]['gbps']} GB/s")
         del sc
+    del ix
+    # writes: a dense set on the same text
+    dset = synth.workload_sweep_set(text, 100_000, 8)
+    dix = mpm.build_ac(dset.patterns, upload=True)
+    wrows, wref, M = [], None, None
+    for name, cap_full, fl in (("CW: count only (capacity 0), per-lane counts", False, 0),
+                               ("ordered list, lane by lane", True, 0),
+                               ("ordered list, dense mode (waves write consecutive slots)", True,
+                                mpm.VARIANT_DENSE)):
+        v = mpm.variant(lane_bytes=L if not fl else 0, block_threads=W, flags=fl)
+        if M is None:
+            c0 = mpm.Scanner(dix, n, capacity=0, var=v)
+            c0.scan_async(dev)
+            torch.cuda.synchronize()
+            M = int(c0.total.item())
+            del c0
+        sc = mpm.Scanner(dix, n, capacity=M if cap_full else 0, var=v)
+        sc.scan_async(dev)
+        torch.cuda.synchronize()
+        assert int(sc.total.item()) == M
+        if cap_full:
+            got = sc.out[:M]
+            if wref is None:
+                wref = got.clone()
+            elif not torch.equal(got, wref):
+                raise SystemExit(f"write row '{name}' reports a different list")
+        kms = time_scans(sc, dev, args.steps, args.warmup, stream)
+        wrows.append({"kernel": name, "kernel_ms": round(kms, 4),
+                      "gbps": round(n / (kms * 1e-3) / 1e9, 2),
+                      "list_bytes": 8 * M if cap_full else 0})
+        log(f"[bench] ablation {name}: {wrows[-1]['gbps']} GB/s")
+        del sc
     line = {"metric": "text GB/s scanned (AC kernel designs)", "workload": "ablation",
-            "config": {"workload": desc, "n_bytes": n, "lane_bytes": L, "block_threads": W,
-                       "matches": int(ref.shape[0]), "states": ix.info()["n_states"]},
+            "config": {"workload": desc, "n_bytes": n, "matches": int(ref.shape[0]),
+                       "states": mpm.build_ac(ps.patterns).info()["n_states"],
+                       "write_set": "d=100000, m=8, 10% planted (the sweep's set) on the same text",
+                       "write_matches": M},
             "steps": args.steps, "warmup": args.warmup, "dtype": "u8", "data": "synthetic",
-            "rows": rows}
+            "rows": rows, "write_rows": wrows}
+    print(json.dumps(line), flush=True)
+
+
+MIXED_DESC = ("EST-shaped DNA text 256 MiB (seed 51), d=1000 patterns of lengths 8-32: 500 text "
+              "windows, 200 of their prefixes, 100 suffixes, 50 duplicates, 150 random (seed 52)")
+
+
+def run_mixed(args):
+    """Pattern sets of different lengths: the reversed-automaton AC scan and
+    the shortest-length WM scan of the 256 MiB EST text, each with its
+    default launch variant, the whole list written; text GB/s, the HBM
+    roofline fraction of the algorithmic bytes (text read once, list written
+    once), and the list's count and digest against the oracle's. One JSON
+    line."""
+    import torch
+    import paper_1407_2889_amd as mpm
+    import synth
+    import oracle
+    text = synth.est_text(256 << 20, seed=51)
+    P = synth.mixed_pattern_set(text, 1000, 8, 32, 500, seed=52, n_prefix=200, n_suffix=100,
+                                n_dup=50)
+    n = len(text)
+    dev = torch.from_numpy(text).cuda()
+    stream = torch.cuda.current_stream()
+    log("[bench] mixed lengths: oracle list")
+    want = oracle.parallel_scan(oracle.AC(P), text, workers=HOST_SHARE_THREADS)
+    M = len(want[0])
+    dg = listdigest()
+    want_digest = dg.digest_np(want[0], want[1])
+    rows = []
+    for algo in ("ac", "wm"):
+        ix = (mpm.build_ac_var if algo == "ac" else mpm.build_wm_var)(P, upload=True)
+        inf = ix.info()
+        for pl in (mpm.PLACE_AUTO, mpm.PLACE_HOT, mpm.PLACE_GLOBAL):
+            v = dict(DEFAULT_VARIANTS[algo], placement=pl)
+            sc = mpm.Scanner(ix, n, capacity=M + 64, var=mpm.variant(**v))
+            got = sc.scan(dev)
+            equal = int(got.shape[0]) == M and dg.digest_torch(got) == want_digest
+            kms = time_scans(sc, dev, args.steps, args.warmup, stream)
+            alg = n + 8 * M
+            rows.append({"algo": algo, "variant": v, "kernel_ms": round(kms, 4),
+                         "gbps": round(n / (kms * 1e-3) / 1e9, 2),
+                         "roofline_frac": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "matches": M, "equals_oracle": bool(equal),
+                         "table_bytes": int(inf["table_bytes"]), "m_min": inf["m"],
+                         "m_max": inf["m_max"]})
+            log(f"[bench] mixed {algo} placement {pl}: {rows[-1]['gbps']} GB/s, equals oracle {equal}")
+            del sc
+        del ix
+    if not all(r["equals_oracle"] for r in rows):
+        raise SystemExit("mixed-length lists differ from the oracle's")
+    line = {"metric": "text GB/s scanned (pattern sets of different lengths)", "workload": "mixed",
+            "config": {"workload": MIXED_DESC, "n_bytes": n}, "steps": args.steps,
+            "warmup": args.warmup, "dtype": "u8", "data": "synthetic", "rows": rows}
     print(json.dumps(line), flush=True)
 
 
@@ -528,6 +643,8 @@ def main():
         return run_ablation(args)
     if args.workload == "scaling":
         return run_scaling(args)
+    if args.workload == "mixed":
+        return run_mixed(args)
 
     import torch
     import paper_1407_2889_amd as mpm

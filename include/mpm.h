@@ -126,6 +126,18 @@ typedef struct {
  * ignores the flag. EUNSUPPORTED with MPM_VARIANT_ILP2 or
  * MPM_VARIANT_SUPPLY. */
 #define MPM_VARIANT_DENSE 8u
+/* Text access of the paper's kernel ladder (Section 4.2.2), kept to measure
+ * what line streaming buys; Aho-Corasick with 16-bit table entries, fixed
+ * pattern length, placement LDS or GLOBAL, the byte -> column table in LDS,
+ * single-text scans only (a batch plan ignores them). TEXT_BYTES: every
+ * lane reads its bytes one at a time from global memory (the unoptimised
+ * kernel's reads). TEXT_LDS: the workgroup first copies its chunk's text
+ * (and the m - 1 bytes after it) into LDS with coalesced 16-byte loads, then
+ * every lane walks its bytes from LDS (the staged-text kernel); needs
+ * lane_bytes * block_threads + m + 47 bytes of LDS beside the tables.
+ * EUNSUPPORTED together, or with ILP2, SUPPLY, DENSE or the hot placement. */
+#define MPM_VARIANT_TEXT_BYTES 16u
+#define MPM_VARIANT_TEXT_LDS 32u
 
 /* Facts about a built index. */
 typedef struct {
@@ -189,8 +201,7 @@ mpm_status mpm_build_wm(const uint8_t *patterns, uint32_t d, uint32_t m,
  * mpm_build_wm. Indexes of several lengths run in single-text scans
  * (mpm_scan, mpm_scan_sync, mpm_scan_noalloc) with one range per lane and
  * per-lane output: MPM_VARIANT_ILP2, _SUPPLY and _DENSE, batches, tuning and
- * mpm_scan_host give EUNSUPPORTED, as does opts->ac_goto; the Aho-Corasick
- * walk has no hot placement.
+ * mpm_scan_host give EUNSUPPORTED, as does opts->ac_goto.
  * Errors: EINVAL (null pointer, d == 0, an empty pattern or descending
  * offsets), ETOOBIG (more than 2^31 automaton states, 4 GiB of distinct
  * pattern bytes or 2^31 id-list entries), EUNSUPPORTED (wm_block outside

@@ -60,6 +60,8 @@ VARIANT_NO_SWAR = 1
 VARIANT_ILP2 = 2
 VARIANT_SUPPLY = 4
 VARIANT_DENSE = 8
+VARIANT_TEXT_BYTES = 16
+VARIANT_TEXT_LDS = 32
 
 
 class Variant(C.Structure):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmpm.so")
 SOURCES = [  # longest compiles first (parallel build)
-    "mpm_scan_var.hip", "mpm_scan_ac16_hot.hip", "mpm_scan_ac16_glb.hip", "mpm_scan_ac16_lds.hip",
+    "mpm_scan_var.hip", "mpm_scan_ladder.hip", "mpm_scan_ac16_hot.hip", "mpm_scan_ac16_glb.hip", "mpm_scan_ac16_lds.hip",
     "mpm_scan_ac_supply.hip", "mpm_scan_batch_other.hip", "mpm_scan_ac32_glb.hip",
     "mpm_scan_batch_ac16_hot.hip", "mpm_scan_batch_ac16_glb.hip", "mpm_scan_batch_ac16_lds.hip",
     "mpm_scan_wm.hip", "mpm_host.cpp", "mpm_scan.hip", "mpm_mlp.hip", "mpm_count.hip",

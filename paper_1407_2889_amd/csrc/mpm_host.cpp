@@ -1138,7 +1138,7 @@ mpm_status mpm_batch_plan(const mpm_request *reqs, uint32_t count, mpm_batch **o
             }
             mpm_variant v = r.variant;
             // batched walkers run one range per lane and write per lane
-            v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
+            v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE | MPM_VARIANT_TEXT_BYTES | MPM_VARIANT_TEXT_LDS);
             Item it;
             it.req = k;
             it.ix = r.idx;
@@ -1268,7 +1268,7 @@ mpm_status mpm_batch_launch_key(const mpm_index *idx, const mpm_variant *variant
         return fail(MPM_EUNSUPPORTED, "mpm_batch_launch_key: sets of different lengths run in "
                     "single-text scans only");
     mpm_variant v = variant ? *variant : mpm_variant{0, 0, 0, 0, 0};
-    v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
+    v.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE | MPM_VARIANT_TEXT_BYTES | MPM_VARIANT_TEXT_LDS);
     LaunchCfg cfg;
     mpm_status st = resolve_variant(idx, &v, 0, &cfg);
     if (st)
@@ -1432,7 +1432,7 @@ static mpm_status tune_layout(const mpm_index *idx, uint64_t n, uint32_t copies,
         return fail(MPM_EUNSUPPORTED, "mpm_tune: sets of different lengths run in single-text "
                     "scans only");
     mpm_variant w = v ? *v : mpm_variant{0, 0, 0, 0, 0};
-    w.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE);
+    w.flags &= ~(MPM_VARIANT_ILP2 | MPM_VARIANT_DENSE | MPM_VARIANT_TEXT_BYTES | MPM_VARIANT_TEXT_LDS);
     mpm_status st = resolve_variant(idx, &w, 0, cfg);
     if (st)
         return st;

@@ -267,6 +267,8 @@ struct LaunchCfg {
     uint32_t csr_lds;     // LDS byte offset of the id CSR (0: global memory)
     bool dense;           // dense output (position marks in LDS)
     uint32_t mark_lds;    // LDS byte offset of the marks (dense)
+    uint32_t text_mode;   // 0: line streaming; 1: bytes from global; 2: text staged in LDS
+    uint32_t text_lds;    // text_mode 2: LDS byte offset of the staged text
 };
 // LDS bytes of the dense output's position marks (1024 lanes x 16 positions).
 static const uint32_t DENSE_MARK_BYTES = 1024 * 16 * 4;
@@ -291,6 +293,9 @@ WmDev wm_dev(const mpm_index *ix);
 mpm_status build_ac_rev_tables(mpm_index *ix);
 const void *var_kernel(const mpm_index *ix, const LaunchCfg &c);
 mpm_status var_launch(const mpm_index *ix, const LaunchCfg &c, const ScanDev &sd, void *stream);
+// Text-access ladder variants (mpm_scan_ladder.hip).
+const void *ladder_kernel(const mpm_index *ix, const LaunchCfg &c);
+mpm_status ladder_launch(const mpm_index *ix, const LaunchCfg &c, const ScanDev &sd, void *stream);
 uint32_t batch_kind(const mpm_index *ix, const LaunchCfg &c);
 // Batched launches run one kernel per walker kind (BK_*, with BK_SWAR).
 uint32_t batch_grid(uint32_t kind, uint32_t W, uint32_t lds_bytes, uint64_t ntiles,

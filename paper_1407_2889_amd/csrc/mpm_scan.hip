@@ -165,9 +165,7 @@ WmDev wm_dev(const mpm_index *ix)
 // Whether an index can run with the hot part of its tables in LDS.
 static bool has_hot(const mpm_index *ix)
 {
-    // the reversed walk of sets of different lengths reads the whole table
-    // from one place
-    return ix->algo == MPM_ALGO_WM || (ix->algo == MPM_ALGO_AC && !ix->var);
+    return ix->algo == MPM_ALGO_WM || ix->algo == MPM_ALGO_AC;
 }
 
 // LDS bytes of the hot part (reserve: bytes the launch keeps beside it).
@@ -182,6 +180,8 @@ static const void *kernel_for(const mpm_index *ix, const LaunchCfg &c)
 {
     if (ix->var)
         return var_kernel(ix, c);
+    if (c.text_mode)
+        return ladder_kernel(ix, c);
     if (ix->algo == MPM_ALGO_AC && c.supply)
         return ac_supply_kernel(ix->state_bytes, c);
     if (ix->algo == MPM_ALGO_AC) {
@@ -216,8 +216,20 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
         return fail(MPM_EINVAL, "variant: block_threads=%u must be 256, 512 or 1024", W);
     if (d.placement > MPM_PLACE_HOT)
         return fail(MPM_EINVAL, "variant: unknown placement %u", d.placement);
-    if (d.flags & ~(MPM_VARIANT_NO_SWAR | MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY | MPM_VARIANT_DENSE))
+    if (d.flags & ~(MPM_VARIANT_NO_SWAR | MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY | MPM_VARIANT_DENSE |
+                    MPM_VARIANT_TEXT_BYTES | MPM_VARIANT_TEXT_LDS))
         return fail(MPM_EINVAL, "variant: unknown flags 0x%x", d.flags);
+    const uint32_t text_flags = d.flags & (MPM_VARIANT_TEXT_BYTES | MPM_VARIANT_TEXT_LDS);
+    if (text_flags) {
+        if (text_flags == (MPM_VARIANT_TEXT_BYTES | MPM_VARIANT_TEXT_LDS) ||
+            (d.flags & (MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY | MPM_VARIANT_DENSE)) ||
+            d.placement == MPM_PLACE_HOT)
+            return fail(MPM_EUNSUPPORTED, "variant: the text-access variants are one alone, one "
+                        "chain per lane, tables in LDS or global memory");
+        if (ix->algo != MPM_ALGO_AC || ix->var || ix->state_bytes != 2)
+            return fail(MPM_EUNSUPPORTED, "variant: the text-access variants run Aho-Corasick "
+                        "with 16-bit entries and one pattern length");
+    }
     const bool dense = (d.flags & MPM_VARIANT_DENSE) != 0;
     if (dense && (d.flags & (MPM_VARIANT_ILP2 | MPM_VARIANT_SUPPLY)))
         return fail(MPM_EUNSUPPORTED, "variant: dense output runs the flattened walk, one range "
@@ -241,11 +253,18 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     // dynamic LDS: the kernels' fixed header and byte-class regions, then the
     // tables when they are placed in LDS
     const uint32_t fixed = LDS_FIXED_BYTES;
-    const uint32_t reserve = dense ? DENSE_MARK_BYTES : 0u;  // LDS kept for the marks
+    // LDS kept beside the tables: the dense marks, or the staged text
+    const uint32_t stage_bytes =
+        (text_flags & MPM_VARIANT_TEXT_LDS)
+            ? (uint32_t)(((uint64_t)L * W + ix->m + 47) / 16 * 16)
+            : 0u;
+    const uint32_t reserve = dense ? DENSE_MARK_BYTES : stage_bytes;
     const uint64_t table_lds = fixed + reserve + (supply ? ix->go_bytes : ix->table_bytes);
     const bool fits = table_lds <= (uint64_t)lim.max_lds;
     const bool ilp2 = ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2);
-    const bool hot_ok = has_hot(ix) && !ilp2 && !supply &&
+    if (fixed + reserve > (uint64_t)lim.max_lds)
+        return fail(MPM_EUNSUPPORTED, "variant: %u bytes of staged text exceed LDS", reserve);
+    const bool hot_ok = has_hot(ix) && !ilp2 && !supply && !text_flags &&
                         fixed + reserve + hot_lds_bytes(ix, reserve) <= (uint64_t)lim.max_lds;
     uint32_t place = d.placement;
     if (place == MPM_PLACE_AUTO)
@@ -261,7 +280,8 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
     cfg->placement = place;
     cfg->supply = supply;
     cfg->swar = ix->algo == MPM_ALGO_AC && ix->swar_ok && !(d.flags & MPM_VARIANT_NO_SWAR) &&
-                !supply;
+                !supply && !text_flags;
+    cfg->text_mode = (text_flags & MPM_VARIANT_TEXT_BYTES) ? 1u : (text_flags ? 2u : 0u);
     cfg->ilp = (ix->algo == MPM_ALGO_AC && (d.flags & MPM_VARIANT_ILP2)) ? 2 : 1;
     cfg->lds_bytes = fixed + (place == MPM_PLACE_LDS   ? (uint32_t)(supply ? ix->go_bytes
                                                                            : ix->table_bytes)
@@ -269,6 +289,7 @@ mpm_status resolve_variant(const mpm_index *ix, const mpm_variant *v, uint64_t n
                                                        : 0u);
     cfg->dense = dense;
     cfg->mark_lds = dense ? cfg->lds_bytes : 0u;
+    cfg->text_lds = stage_bytes ? cfg->lds_bytes : 0u;
     cfg->lds_bytes += reserve;
     cfg->csr_lds = 0;
     if (csr_in_lds) {
@@ -313,6 +334,8 @@ mpm_status launch_scan(const mpm_index *ix, const LaunchCfg &c, const ScanDev &s
                             (int)c.lds_bytes);
     if (ix->var)
         return var_launch(ix, c, sd, stream);
+    if (c.text_mode)
+        return ladder_launch(ix, c, sd, stream);
     if (ix->algo == MPM_ALGO_AC && c.supply) {
         e = ac_supply_launch(ix->state_bytes, ac_dev(ix), c, sd, s);
     } else if (ix->algo == MPM_ALGO_AC) {

@@ -450,6 +450,7 @@ struct AcWalk {
     using Dev = AcDev;
     static constexpr int ILP = Ilp;
     static constexpr bool DESC = false;  // reports starts in ascending order
+    static constexpr bool STAGE = false;  // reads text through registers
     static constexpr bool InLds = P == PL_LDS;
     // PL_HOT: states below hot (the first rows in breadth-first order, where
     // a walk over text spends nearly all its steps) are read from LDS, the
@@ -976,6 +977,7 @@ struct AcSupplyWalk {
     using Dev = AcDev;
     static constexpr int ILP = 1;
     static constexpr bool DESC = false;
+    static constexpr bool STAGE = false;  // reads text through registers
     static constexpr bool InLds = P == PL_LDS;
     static constexpr uint32_t FAIL = sizeof(St) == 2 ? 0xffffu : 0xffffffffu;
     typename TabPtr<InLds, uint8_t>::type gob;  // goto rows, addressed in bytes
@@ -1063,9 +1065,12 @@ struct AcSupplyWalk {
 // Aho-Corasick over the reversed strings (sets of different lengths)
 // ---------------------------------------------------------------------------
 // Bytes [a, e) of a text from e - 1 down to a: single bytes down to a 16-byte
-// boundary, 16-byte pieces, then single bytes. one(byte, pos) and
-// sixteen(v4u, pos of its first byte) consume; a piece's bytes are taken
-// from its last to its first.
+// boundary, 16-byte pieces down to a 128-byte boundary, whole 128-byte lines
+// (eight 16-byte loads issued together, the next lower line's loads issued
+// before the current one is consumed: a line read piece by piece is often
+// evicted from L2 between its pieces), then 16-byte pieces and single bytes.
+// one(byte, pos) and sixteen(v4u, pos of its first byte) consume; a piece's
+// bytes are taken from its last to its first.
 template <class F1, class F16>
 __device__ __forceinline__ void rstream_text(glb_cptr<uint8_t> text, uint64_t a, uint64_t e,
                                              F1 &&one, F16 &&sixteen)
@@ -1074,6 +1079,36 @@ __device__ __forceinline__ void rstream_text(glb_cptr<uint8_t> text, uint64_t a,
     while (p > a && (((uintptr_t)(text + p)) & 15u)) {
         --p;
         one((uint32_t)text[p], p);
+    }
+    while (p >= a + 16 && (((uintptr_t)(text + p)) & 127u)) {
+        p -= 16;
+        sixteen(*(glb_cptr<v4u>)(text + p), p);
+    }
+    if (p >= a + 128) {
+        v4u c[8];
+        {
+            glb_cptr<v4u> q = (glb_cptr<v4u>)(text + p - 128);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                c[j] = q[j];
+        }
+        while (true) {
+            const bool more = p >= a + 256;
+            glb_cptr<v4u> nq = (glb_cptr<v4u>)(text + (more ? p - 256 : p - 128));
+            v4u nx[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                nx[j] = nq[j];
+            p -= 128;
+#pragma unroll
+            for (int j = 7; j >= 0; --j)
+                sixteen(c[j], p + 16 * j);
+            if (!more)
+                break;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                c[j] = nx[j];
+        }
     }
     while (p >= a + 16) {
         p -= 16;
@@ -1098,11 +1133,15 @@ struct AcRevWalk {
     using Dev = AcDev;
     static constexpr int ILP = 1;
     static constexpr bool DESC = true;
+    static constexpr bool STAGE = false;  // reads text through registers
     static constexpr bool InLds = P == PL_LDS;
+    // PL_HOT: the first rows (breadth-first, the short labels a walk spends
+    // most steps in) from LDS, the others from global memory.
+    static constexpr bool Hot = P == PL_HOT;
     typename TabPtr<InLds, uint8_t>::type dfab;  // table, addressed in bytes
     lds_cptr<uint16_t> cls;                      // column byte offset per byte value
     glb_cptr<uint32_t> term;                     // string of each reporting state
-    uint32_t rowb, first_term, mx;
+    uint32_t rowb, first_term, mx, hot;
 
     template <int W>
     __device__ __forceinline__ static void load(const AcDev &a)
@@ -1110,6 +1149,8 @@ struct AcRevWalk {
         copy_to_lds<W>(LDS_CLS_OFF, a.cls, 512);
         if (InLds)
             copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.dfa_bytes);
+        if (Hot)
+            copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.hot_bytes);
     }
 
     __device__ __forceinline__ void bind(const AcDev &a)
@@ -1123,6 +1164,7 @@ struct AcRevWalk {
         else
             dfab = (glb_cptr<uint8_t>)a.dfa;
         term = (glb_cptr<uint32_t>)a.term_u;
+        hot = a.hot_states;
     }
 
     template <int W>
@@ -1136,6 +1178,10 @@ struct AcRevWalk {
     __device__ __forceinline__ uint32_t next(uint32_t s, uint32_t coloff) const
     {
         const uint32_t off = sizeof(St) == 2 ? __umul24(s, rowb) + coloff : s * rowb + coloff;
+        if constexpr (Hot) {
+            if (s < hot)
+                return *(lds_cptr<St>)(lds_at<const uint8_t>(LDS_TAB_OFF) + off);
+        }
         return *(typename TabPtr<InLds, St>::type)(dfab + off);
     }
 
@@ -1184,6 +1230,104 @@ struct AcRevWalk {
 };
 
 // ---------------------------------------------------------------------------
+// Aho-Corasick with the text read a byte at a time (the kernel ladder)
+// ---------------------------------------------------------------------------
+// TM 1: every lane loads its bytes one at a time from global memory. TM 2:
+// the workgroup copies its chunk's text (and the m - 1 bytes after it) into
+// LDS with coalesced 16-byte loads before the walk (stage), and lanes read
+// their bytes from there. Byte q of the chunk starting at base sits at LDS
+// offset tl + sh + (q - base), sh being the text address's offset within 16
+// bytes, so the copy's 16-byte pieces land on 16-byte LDS boundaries. The
+// byte -> column map is the LDS table (no register byte classes).
+template <typename St, int P, int TM>
+struct AcTextWalk {
+    using Dev = AcDev;
+    static constexpr int ILP = 1;
+    static constexpr bool DESC = false;
+    static constexpr bool STAGE = TM == 2;
+    static constexpr bool InLds = P == PL_LDS;
+    typename TabPtr<InLds, uint8_t>::type dfab;
+    lds_cptr<uint16_t> cls;
+    uint32_t rowb, first_term, m, tl;
+
+    template <int W>
+    __device__ __forceinline__ void setup(const AcDev &a, uint32_t text_lds)
+    {
+        copy_to_lds<W>(LDS_CLS_OFF, a.cls, 512);
+        if (InLds)
+            copy_to_lds<W>(LDS_TAB_OFF, (const uint8_t *)a.dfa, a.dfa_bytes);
+        rowb = a.cp * (uint32_t)sizeof(St);
+        first_term = a.first_term;
+        m = a.m;
+        cls = lds_at<const uint16_t>(LDS_CLS_OFF);
+        if constexpr (InLds)
+            dfab = lds_at<const uint8_t>(LDS_TAB_OFF);
+        else
+            dfab = (glb_cptr<uint8_t>)a.dfa;
+        tl = text_lds;
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ uint32_t next(uint32_t s, uint32_t coloff) const
+    {
+        const uint32_t off = sizeof(St) == 2 ? __umul24(s, rowb) + coloff : s * rowb + coloff;
+        return *(typename TabPtr<InLds, St>::type)(dfab + off);
+    }
+
+    // Copy text [base, base + bytes) into LDS (TM 2; no barrier).
+    template <int W>
+    __device__ __forceinline__ void stage(glb_cptr<uint8_t> text, uint64_t base, uint64_t bytes) const
+    {
+        const uint32_t sh = (uint32_t)((uintptr_t)(text + base) & 15u);
+        LDS_AS uint8_t *d = lds_at<uint8_t>(tl);
+        const uint64_t head = min((uint64_t)((16u - sh) & 15u), bytes);
+        if (threadIdx.x < head)
+            d[sh + threadIdx.x] = text[base + threadIdx.x];
+        const uint64_t nw = (bytes - head) / 16;
+        glb_cptr<v4u> src = (glb_cptr<v4u>)(text + base + head);
+        LDS_AS v4u *dst = (LDS_AS v4u *)(d + sh + head);
+        for (uint64_t k = threadIdx.x; k < nw; k += W)
+            dst[k] = src[k];
+        for (uint64_t k = head + nw * 16 + threadIdx.x; k < bytes; k += W)
+            d[sh + k] = text[base + k];
+    }
+
+    template <class F>
+    __device__ __forceinline__ void lane(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                         uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        if (lo >= hi)
+            return;
+        uint64_t end = base + hi + m - 1;
+        if (end > n)
+            end = n;
+        uint32_t s = 0;
+        if constexpr (TM == 2) {
+            lds_cptr<uint8_t> d =
+                lds_at<const uint8_t>(tl + (uint32_t)((uintptr_t)(text + base) & 15u));
+            for (uint32_t q = lo; q < (uint32_t)(end - base); ++q) {
+                s = next(s, cls[d[q]]);
+                if (s >= first_term)
+                    cb(base + q + 1 - m, s - first_term);
+            }
+        } else {
+            for (uint64_t q = base + lo; q < end; ++q) {
+                s = next(s, cls[text[q]]);
+                if (s >= first_term)
+                    cb(q + 1 - m, s - first_term);
+            }
+        }
+    }
+
+    template <class F>
+    __device__ __forceinline__ void lane_again(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                               uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        lane(text, n, base, lo, hi, cb);
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Wu-Manber walker
 // ---------------------------------------------------------------------------
 static const int WM_QUEUE = 4;  // filtered candidates kept before exact checks
@@ -1204,6 +1348,7 @@ struct WmWalk {
     using Dev = WmDev;
     static constexpr int ILP = 1;
     static constexpr bool DESC = false;
+    static constexpr bool STAGE = false;  // reads text through registers
     static constexpr bool InLds = P == PL_LDS;
     // PL_HOT: SHIFT (read for every window) in LDS, the buckets (read only
     // for windows with a zero shift) in global memory.
@@ -1425,6 +1570,12 @@ __device__ __forceinline__ void process_chunk(const Walk &wk, glb_cptr<uint8_t> 
     const uint64_t ns = n - m + 1;
     const uint64_t base = lt * chunk;
     const uint64_t starts = (ns - base) < chunk ? (ns - base) : chunk;
+
+    if constexpr (Walk::STAGE) {  // the chunk's text (and m - 1 bytes) into LDS
+        const uint64_t bytes = (starts + m - 1) < (n - base) ? (starts + m - 1) : (n - base);
+        wk.template stage<W>(text, base, bytes);
+        __syncthreads();
+    }
 
     // Virtual lane v of this thread owns starts [lo[v], hi[v]) of the chunk.
     uint32_t lo[I], hi[I];

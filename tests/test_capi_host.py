@@ -280,3 +280,28 @@ def test_supply_walk_variant_resolution():
     with pytest.raises(mpm.MpmError) as e:
         mpm.workspace_bytes(withgo, 1 << 20, mpm.variant(64, 256, 0, 0, 8))
     assert e.value.status == mpm.MPM_EINVAL
+
+
+def test_text_access_variant_resolution():
+    """The ladder's text-access variants: Aho-Corasick with 16-bit entries
+    and one pattern length, one at a time, one chain per lane, tables in LDS
+    or global memory; the staged text must fit in LDS beside the tables.
+    Host-only."""
+    rng = np.random.default_rng(29)
+    P = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, (60, 8))]
+    ac, wm = mpm.build_ac(P), mpm.build_wm(P)
+    tb, tl = mpm.VARIANT_TEXT_BYTES, mpm.VARIANT_TEXT_LDS
+    for fl in (tb, tl):
+        for pl in (mpm.PLACE_AUTO, mpm.PLACE_LDS, mpm.PLACE_GLOBAL):
+            assert mpm.workspace_bytes(ac, 1 << 20, mpm.variant(64, 256, pl, 0, fl)) > 0
+    bad = [(ac, mpm.PLACE_AUTO, tb | tl), (ac, mpm.PLACE_HOT, tb), (ac, mpm.PLACE_AUTO, tl | mpm.VARIANT_ILP2),
+           (wm, mpm.PLACE_AUTO, tb), (mpm.build_ac_var([b"ACG", b"ACGTT"]), mpm.PLACE_AUTO, tl),
+           (ac, mpm.PLACE_AUTO, tl | mpm.VARIANT_SUPPLY)]
+    for ix, pl, fl in bad:
+        with pytest.raises(mpm.MpmError) as e:
+            mpm.workspace_bytes(ix, 1 << 20, mpm.variant(64, 256, pl, 0, fl))
+        assert e.value.status == mpm.MPM_EUNSUPPORTED, (pl, fl)
+    # 4096-byte lanes of 1024 threads: 4 MiB of text cannot be staged
+    with pytest.raises(mpm.MpmError) as e:
+        mpm.workspace_bytes(ac, 1 << 24, mpm.variant(4096, 1024, mpm.PLACE_GLOBAL, 0, tl))
+    assert e.value.status == mpm.MPM_EUNSUPPORTED

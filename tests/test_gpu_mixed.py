@@ -60,9 +60,8 @@ VARIANTS = [dict(lane_bytes=16, block_threads=256), dict(lane_bytes=64, block_th
 
 
 def variants_for(mpm, ix, algo):
-    vs = list(VARIANTS)
-    if algo == "wm":
-        vs.append(dict(lane_bytes=64, block_threads=512, placement=3))
+    vs = list(VARIANTS) + [dict(lane_bytes=64, block_threads=512, placement=3),
+                           dict(lane_bytes=1024, block_threads=1024, placement=3)]
     out = []
     for v in vs:
         var = mpm.variant(**v)

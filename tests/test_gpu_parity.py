@@ -112,7 +112,7 @@ def edge_cases():
 
 
 @pytest.mark.parametrize("case", edge_cases(), ids=lambda c: c[0])
-@pytest.mark.parametrize("algo", ["ac", "wm", "ac-supply"])
+@pytest.mark.parametrize("algo", ["ac", "wm", "ac-supply", "ac-text"])
 def test_edge_cases(mpm, case, algo):
     name, T, P = case
     want = oracle.Win(P).scan(T)
@@ -129,10 +129,23 @@ def test_edge_cases(mpm, case, algo):
                 dict(block_threads=1024, placement=2, flags=mpm.VARIANT_DENSE))
     if algo == "ac-supply":
         variants = tuple(dict(v, flags=mpm.VARIANT_SUPPLY) for v in variants if not v.get("flags"))
+    if algo == "ac-text":
+        # the text-access variants of the kernel ladder: bytes from global
+        # memory, or the chunk's text staged in LDS
+        variants = tuple(dict(lane_bytes=L, block_threads=W, placement=pl, flags=f)
+                         for L, W in ((16, 256), (64, 1024), (48, 512))
+                         for pl in (1, 2)
+                         for f in (mpm.VARIANT_TEXT_BYTES, mpm.VARIANT_TEXT_LDS))
     for mis in (0, 3):
         for v in variants:
             say(f"[edge {name} n={len(T)} d={len(P)} m={P.shape[1]}] {algo} misalign={mis} {v}")
-            got = gpu_pairs(mpm, ix, T, mpm.variant(**v), misalign=mis)
+            try:
+                got = gpu_pairs(mpm, ix, T, mpm.variant(**v), misalign=mis)
+            except mpm.MpmError as e:
+                # ladder variants: 32-bit tables, or LDS tables beside the staged text
+                if algo == "ac-text" and e.status == mpm.MPM_EUNSUPPORTED:
+                    continue
+                raise
             assert_same(got, want, f"{name} {algo} mis={mis} {v}")
 
 
