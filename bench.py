@@ -47,17 +47,23 @@ DENSE_VARIANT = dict(block_threads=1024, placement=0, flags=8)
 METRIC = "text GB/s scanned (AC, WM) + %HBM roofline; learned vs exhaustive-tuned GB/s"
 
 
+# The sources the single-text AC and WM scan kernels and their launches are
+# built from (the kernels' template code, its launch and workspace set-up).
+SCAN_SOURCES = ("mpm_internal.h", "mpm_scan_impl.h", "mpm_scan.hip", "mpm_scan_ac16_lds.hip",
+                "mpm_scan_wm.hip", "mpm_host.cpp")
+
+
 def kernel_digest() -> str:
-    """Hash of the scan library's kernel and host sources: counter records
-    taken from an older build stop applying once it changes."""
+    """Hash of the sources of the single-text scan kernels and their launch:
+    counter records taken from an older build stop applying once it
+    changes."""
     import hashlib
     d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1407_2889_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in SCAN_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -77,6 +83,27 @@ def recorded_traffic(workload: str, algo: str):
         return None
     k = rec["kernels"][algo]
     return int(round(1024 * (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"])))
+
+
+# MI355X compute units and engine clock (GHz) for the LDS ceiling.
+CUS, CLOCK_GHZ = 256, 2.4
+
+
+def recorded_lds(workload: str, algo: str):
+    """LDS-active cycles per wave-wide LDS read and LDS reads per 64 text
+    bytes of the `algo` scan kernel on `workload`, from the committed
+    rocprofv3 record (SQ_LDS_IDX_ACTIVE / SQ_INSTS_LDS, bank conflicts
+    included), or None when absent or taken from older kernel sources."""
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                     f"scan_{workload}_lds_counters.md")
+    try:
+        with open(p) as f:
+            rec = next(json.loads(l[len("lds: "):]) for l in f if l.startswith("lds: "))
+    except (OSError, StopIteration, ValueError):
+        return None
+    if rec.get("digest") != kernel_digest() or algo not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][algo]
 
 
 def log(*a):
@@ -207,8 +234,12 @@ def run_sweep(args):
     stream = torch.cuda.current_stream()
     rows = []
     t_all = 0.0
+    only = ({tuple(int(x) for x in dm.split(":")) for dm in args.sweep_sets.split(",")}
+            if args.sweep_sets else None)
     for d in synth.SWEEP_D:
         for m in synth.SWEEP_M:
+            if only is not None and (d, m) not in only:
+                continue
             ps = synth.workload_sweep_set(text, d, m)
             lists = {}
             for algo in ("ac", "wm"):
@@ -627,6 +658,8 @@ def main():
     ap.add_argument("--wm", default=None, help="WM variant as L,W,placement[,flags]")
     ap.add_argument("--train-requests", type=int, default=5000, help="batch: timing database size")
     ap.add_argument("--batch-texts", type=int, default=4096, help="batch: texts in the batch")
+    ap.add_argument("--sweep-sets", default=None,
+                    help="sweep: only these sets, as d:m pairs separated by commas")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -750,6 +783,23 @@ def main():
                      "traffic": recorded_traffic(args.workload, dom),
                      "alg_bytes_per_launch": alg_bytes},
     }
+    lds = recorded_lds(args.workload, dom)
+    if lds is not None and ix[dom].info()["table_bytes"] + 1536 <= 160 * 1024:
+        # The walk makes one dependent table lookup per text byte from LDS:
+        # its ceiling is the rate at which the CUs' LDS serves the kernel's
+        # wave-wide reads at their measured cost (bank conflicts included).
+        ceiling = CUS * CLOCK_GHZ * 64 / (lds["lds_cycles_per_instr"] * lds["lds_instr_per_64_bytes"])
+        hbm = line["roofline"]
+        line["roofline"] = {
+            "bound": "lds", "kernel": hbm["kernel"], "achieved": round(gbs[dom], 2),
+            "peak": round(ceiling, 1), "unit": "GB/s", "frac": round(gbs[dom] / ceiling, 4),
+            "traffic": hbm["traffic"], "alg_bytes_per_launch": alg_bytes,
+            "peak_basis": (f"text bytes per second at one LDS table lookup per byte: {CUS} CUs x "
+                           f"{CLOCK_GHZ} GHz x 64 lanes per wave-wide LDS read / "
+                           f"({lds['lds_cycles_per_instr']} LDS-active cycles per read x "
+                           f"{lds['lds_instr_per_64_bytes']} reads per 64 text bytes), both "
+                           "from rocprofv3 SQ_LDS_IDX_ACTIVE and SQ_INSTS_LDS"),
+            "hbm": {"achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "frac": hbm["frac"]}}
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(text, P, min(n, args.cpu_sample_mib << 20))
