@@ -38,11 +38,20 @@ def test_counter_record_matches_current_kernels():
 
 
 def test_digest_changes_with_sources(tmp_path, monkeypatch):
-    """A different source tree hashes differently (the record then no longer
-    applies)."""
+    """A change to any source of the single-text scan kernels hashes
+    differently (the record then no longer applies); other sources do not
+    enter the digest."""
+    import shutil
     d0 = bench.kernel_digest()
+    src = os.path.join(os.path.dirname(bench.__file__), "paper_1407_2889_amd", "csrc")
     csrc = tmp_path / "paper_1407_2889_amd" / "csrc"
     csrc.mkdir(parents=True)
-    (csrc / "k.hip").write_text("// another kernel\n")
+    for f in bench.SCAN_SOURCES:
+        shutil.copy(os.path.join(src, f), csrc / f)
     monkeypatch.setattr(bench, "__file__", str(tmp_path / "bench.py"))
+    assert bench.kernel_digest() == d0
+    (csrc / "unrelated.hip").write_text("// another kernel\n")
+    assert bench.kernel_digest() == d0
+    with open(csrc / "mpm_scan_impl.h", "a") as f:
+        f.write("// changed\n")
     assert bench.kernel_digest() != d0
