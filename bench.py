@@ -535,7 +535,9 @@ def run_scaling(args):
     """Kernel time against the number of busy CUs: the AC and WM scans of the
     first k MiB of the 256 MiB EST text in the benchmark's launch
     configuration (one 1 MiB chunk per workgroup, one workgroup per CU), k
-    from 1 to 256. One JSON line."""
+    from 1 to 256, and the same text read in the scans' lane layout without
+    the walk (1 KiB lanes, and 128-byte lanes for comparison). One JSON
+    line."""
     import torch
     import paper_1407_2889_amd as mpm
     text, ps, desc = workload("est256")
@@ -545,7 +547,7 @@ def run_scaling(args):
     for algo in ("ac", "wm"):
         ix = (mpm.build_ac if algo == "ac" else mpm.build_wm)(ps.patterns, upload=True)
         v = mpm.variant(**DEFAULT_VARIANTS[algo])
-        for k in (1, 8, 64, 128, 192, 256):
+        for k in (1, 8, 64, 128, 192, 224, 240, 256):
             n = min(len(text), k << 20)
             sc = mpm.Scanner(ix, n, capacity=1 << 16, var=v)
             kms = time_scans(sc, dev[:n], args.steps, args.warmup, stream)
@@ -554,6 +556,28 @@ def run_scaling(args):
             log(f"[bench] scaling {algo} {k} chunks: {rows[-1]['kernel_us']} us")
             del sc
         del ix
+    # the same lane layout read without the table walk: the memory system's
+    # rate for the scans' access pattern
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for lane in (1024, 128):
+        for k in (1, 8, 64, 128, 192, 256):
+            n = min(len(text), k << 20)
+            buf = dev[:n]
+            for _ in range(args.warmup):
+                mpm.read_probe_lanes(buf, lane, sink)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            for a, b in ev:
+                a.record(stream)
+                mpm.read_probe_lanes(buf, lane, sink)
+                b.record(stream)
+            torch.cuda.synchronize()
+            kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+            rows.append({"algo": f"read_lanes_{lane}", "chunks": n // (1024 * lane),
+                         "mib": n >> 20, "kernel_us": round(kms * 1e3, 2),
+                         "gbps": round(n / (kms * 1e-3) / 1e9, 2)})
+            log(f"[bench] scaling read lanes {lane} B, {n >> 20} MiB: {rows[-1]['kernel_us']} us")
     line = {"metric": "kernel time against busy CUs", "workload": "scaling",
             "config": {"workload": desc, "variants": DEFAULT_VARIANTS}, "steps": args.steps,
             "warmup": args.warmup, "dtype": "u8", "data": "synthetic", "rows": rows}

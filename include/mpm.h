@@ -493,6 +493,15 @@ mpm_status mpm_export_unique(const mpm_index *idx, uint32_t *uoff, uint32_t *ids
  * sentinel. Errors: EINVAL, EHIP. */
 mpm_status mpm_read_probe(const uint8_t *d_buf, uint64_t bytes, uint32_t *d_sink, void *stream);
 
+/* Read `bytes` of d_buf (128-byte aligned) in the scans' text access
+ * pattern, without their table walk: 1024-thread workgroups, each lane
+ * reading its own lane_bytes range (a multiple of 128) as whole 128-byte
+ * lines with the next line in flight, lanes' ranges side by side, one chunk
+ * of 1024 ranges per workgroup; `bytes` a multiple of 1024 * lane_bytes.
+ * Measurement only, as mpm_read_probe. Errors: EINVAL, EHIP. */
+mpm_status mpm_read_probe_lanes(const uint8_t *d_buf, uint64_t bytes, uint32_t lane_bytes,
+                                uint32_t *d_sink, void *stream);
+
 /* Last error message of this thread ("" if none). */
 const char *mpm_last_error(void);
 

@@ -132,6 +132,7 @@ _sig("mpm_export_ac", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_export_wm_shift", C.c_int32, [_vp, _vp])
 _sig("mpm_export_unique", C.c_int32, [_vp, _vp, _vp])
 _sig("mpm_read_probe", C.c_int32, [_vp, _u64, _vp, _vp])
+_sig("mpm_read_probe_lanes", C.c_int32, [_vp, _u64, _u32, _vp, _vp])
 _sig("mpm_count_ids", C.c_int32, [_vp, _u64, _u32, _vp, _vp])
 _sig("mpm_scan_host", C.c_int32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _u64, _vp, _u64, _vp,
                                   C.POINTER(Variant), _vp, C.POINTER(_u64)])
@@ -156,7 +157,7 @@ EXPORTS = [
     "mpm_tune_time", "mpm_tune_work_bytes", "mpm_mlp_act_floats", "mpm_mlp_forward",
     "mpm_mlp_loss_grad", "mpm_mlp_backward", "mpm_mlp_adam", "mpm_count_ids",
     "mpm_scan_host", "mpm_scan_noalloc", "mpm_batch_launch_key", "mpm_build_ac_var",
-    "mpm_build_wm_var",
+    "mpm_build_wm_var", "mpm_read_probe_lanes",
 ]
 
 
@@ -473,6 +474,14 @@ def read_probe(buf, sink, stream=None):
     """Stream-read a 16-byte aligned CUDA tensor once (HBM ceiling probe)."""
     _check(_L.mpm_read_probe(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
                              C.c_void_p(sink.data_ptr()), _stream_handle(stream)), "mpm_read_probe")
+
+
+def read_probe_lanes(buf, lane_bytes: int, sink, stream=None):
+    """Read a 128-byte aligned CUDA tensor in the scans' lane pattern (each
+    of 1024 lanes per workgroup reads its own lane_bytes range by lines)."""
+    _check(_L.mpm_read_probe_lanes(C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                                   lane_bytes, C.c_void_p(sink.data_ptr()), _stream_handle(stream)),
+           "mpm_read_probe_lanes")
 
 
 def pairs_numpy(t) -> tuple[np.ndarray, np.ndarray]:

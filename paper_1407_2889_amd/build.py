@@ -19,7 +19,7 @@ SOURCES = [  # longest compiles first (parallel build)
     "mpm_scan_ac_supply.hip", "mpm_scan_batch_other.hip", "mpm_scan_ac32_glb.hip",
     "mpm_scan_batch_ac16_hot.hip", "mpm_scan_batch_ac16_glb.hip", "mpm_scan_batch_ac16_lds.hip",
     "mpm_scan_wm.hip", "mpm_host.cpp", "mpm_scan.hip", "mpm_mlp.hip", "mpm_count.hip",
-    "mpm_stream.hip", "mpm_noalloc.hip", "mpm_mixed.cpp"]
+    "mpm_stream.hip", "mpm_noalloc.hip", "mpm_mixed.cpp", "mpm_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
