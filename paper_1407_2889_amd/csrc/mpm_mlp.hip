@@ -3,81 +3,180 @@
 //
 // The network predicts, from a request's features, the log-throughput of each
 // scan variant; it is trained on the exhaustive autotuner's timings. It is a
-// few thousand rows by 64 columns: every kernel here is a plain per-element
-// or per-column loop with deterministic summation order (no atomics), which
-// keeps the GPU gradients reproducible and directly comparable with the FP64
-// reference.
+// few thousand rows by 64 columns: every kernel here sums in a fixed order
+// (no atomics), which keeps the GPU gradients reproducible and directly
+// comparable with the FP64 reference.
 #include <hip/hip_runtime.h>
 
 #include "mpm_internal.h"
 
 namespace mpm {
 
-// Y[b, n] = act(bias[n] + sum_k X[b, k] W[k, n]); one thread per output.
+// Y[b, n] = act(bias[n] + sum_k X[b, k] W[k, n]); one thread per output, the
+// layer's weights and bias staged in LDS once per workgroup (W[k, n] with n
+// along the lanes: consecutive words), X[b, k] read as a broadcast.
 template <bool Relu>
-__global__ void dense_fwd(const float *__restrict__ X, const float *__restrict__ W,
-                          const float *__restrict__ bias, float *__restrict__ Y, uint32_t B,
-                          uint32_t K, uint32_t N)
+__global__ __launch_bounds__(1024) void dense_fwd(const float *__restrict__ X,
+                                                  const float *__restrict__ W,
+                                                  const float *__restrict__ bias,
+                                                  float *__restrict__ Y, uint32_t B, uint32_t K,
+                                                  uint32_t N)
 {
+    __shared__ float ws[MPM_MLP_HIDDEN * MPM_MLP_HIDDEN + MPM_MLP_HIDDEN];  // W then bias
+    for (uint32_t i = threadIdx.x; i < K * N + N; i += blockDim.x)
+        ws[i] = i < K * N ? W[i] : bias[i - K * N];
+    __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (uint64_t)B * N)
         return;
     const uint32_t b = (uint32_t)(i / N), n = (uint32_t)(i % N);
-    float acc = bias[n];
+    float acc = ws[K * N + n];
     const float *x = X + (uint64_t)b * K;
+#pragma unroll 8
     for (uint32_t k = 0; k < K; ++k)
-        acc = fmaf(x[k], W[(uint64_t)k * N + n], acc);
+        acc = fmaf(x[k], ws[k * N + n], acc);
     Y[i] = Relu ? fmaxf(acc, 0.f) : acc;
 }
 
 // dX[b, k] = (sum_n dY[b, n] W[k, n]) * [A[b, k] > 0]: gradient through a
-// layer into the previous ReLU output A.
-__global__ void dense_bwd_data(const float *__restrict__ dY, const float *__restrict__ W,
-                               const float *__restrict__ A, float *__restrict__ dX, uint32_t B,
-                               uint32_t K, uint32_t N)
+// layer into the previous ReLU output A. The weights are staged in LDS
+// transposed (W[k, n] at n * K + k, k along the lanes), dY[b, n] is read as a
+// broadcast.
+__global__ __launch_bounds__(1024) void dense_bwd_data(const float *__restrict__ dY,
+                                                       const float *__restrict__ W,
+                                                       const float *__restrict__ A,
+                                                       float *__restrict__ dX, uint32_t B,
+                                                       uint32_t K, uint32_t N)
 {
+    __shared__ float wt[MPM_MLP_HIDDEN * MPM_MLP_HIDDEN];
+    for (uint32_t i = threadIdx.x; i < K * N; i += blockDim.x) {
+        const uint32_t k = i / N, n = i % N;
+        wt[n * K + k] = W[i];
+    }
+    __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (uint64_t)B * K)
         return;
     const uint32_t b = (uint32_t)(i / K), k = (uint32_t)(i % K);
     float acc = 0.f;
     const float *dy = dY + (uint64_t)b * N;
-    const float *w = W + (uint64_t)k * N;
+#pragma unroll 8
     for (uint32_t n = 0; n < N; ++n)
-        acc = fmaf(dy[n], w[n], acc);
+        acc = fmaf(dy[n], wt[n * K + k], acc);
     dX[i] = A[i] > 0.f ? acc : 0.f;
 }
 
-// dW[k, n] = sum_b X[b, k] dY[b, n] and (row k == K) dbias[n] = sum_b dY[b, n].
-// Block (k, n-tile of 64): 4 waves split the batch, lane = column; partial
-// sums combined in LDS in a fixed order.
+// dW[k, n] = sum_b X[b, k] dY[b, n] and (row k == K) dbias[n] = sum_b dY[b, n],
+// as a contraction over the batch in two deterministic stages. Stage one:
+// workgroup (r, q) takes batch rows [r * WROWS, (r + 1) * WROWS) and gradient
+// rows k = 17 q .. 17 q + 16. It stages in LDS, with coalesced loads, those
+// 17 input columns of its batch rows (column K = 1 for the bias, columns past
+// it 0; rows padded to XSTRIDE floats so each is four 16-byte words and one
+// more) and their output gradients dY. Wave w sums batch rows
+// [64 w, 64 w + 64) of the block, lane n column n, 17 accumulators per
+// thread, with no branch in the loop; the four waves' sums are then added in
+// wave order. With one row block the result goes straight to dW (dbias
+// follows dW in the parameter vector); otherwise each block writes its
+// partial gradient and stage two sums the partials in block order.
+static const uint32_t WROWS = 256;
+static const uint32_t WSLOTS = 17;   // gradient rows per workgroup quarter
+static const uint32_t XSTRIDE = 20;  // staged floats per batch row (16-byte aligned)
+
+// Copy count floats into LDS, 256 threads, sixteen loads in flight per thread
+// before their stores (a load-store pair per step would wait out one memory
+// round trip per element).
+__device__ __forceinline__ void stage_lds(float *dst, const float *__restrict__ src, uint32_t count)
+{
+    constexpr uint32_t U = 16;
+    uint32_t i = threadIdx.x;
+    for (; i + (U - 1) * 256 < count; i += U * 256) {
+        float v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            v[u] = src[i + u * 256];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            dst[i + u * 256] = v[u];
+    }
+    for (; i < count; i += 256)
+        dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(256) void dense_bwd_weight(const float *__restrict__ X,
                                                         const float *__restrict__ dY,
-                                                        float *__restrict__ dW,
-                                                        float *__restrict__ dbias, uint32_t B,
+                                                        float *__restrict__ out, uint32_t B,
                                                         uint32_t K, uint32_t N)
 {
-    __shared__ float part[4][64];
-    const uint32_t k = blockIdx.x;  // 0..K (K = bias row)
-    const uint32_t n = blockIdx.y * 64 + (threadIdx.x & 63);
-    const uint32_t w = threadIdx.x >> 6;
-    float acc = 0.f;
-    if (n < N) {
-        for (uint32_t b = w; b < B; b += 4) {
-            const float x = k < K ? X[(uint64_t)b * K + k] : 1.f;
-            acc = fmaf(x, dY[(uint64_t)b * N + n], acc);
+    __shared__ __align__(16) float xs[WROWS * XSTRIDE];
+    __shared__ float ds[WROWS * MPM_MLP_HIDDEN];
+    __shared__ float red[3][WSLOTS][MPM_MLP_HIDDEN];
+    const uint32_t r0 = blockIdx.x * WROWS, k0 = blockIdx.y * WSLOTS;
+    const uint32_t rows = min(WROWS, B - r0);
+    {
+        constexpr uint32_t U = 16;
+        const uint32_t count = rows * XSTRIDE;
+        for (uint32_t i0 = threadIdx.x; i0 < count; i0 += U * 256) {
+            float v[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t i = i0 + u * 256;
+                const uint32_t b = i / XSTRIDE, k = k0 + i % XSTRIDE;
+                v[u] = (i < count && k < K && i % XSTRIDE < WSLOTS)
+                           ? X[(uint64_t)(r0 + b) * K + k]
+                           : (k == K ? 1.f : 0.f);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (i0 + u * 256 < count)
+                    xs[i0 + u * 256] = v[u];
         }
     }
-    part[w][threadIdx.x & 63] = acc;
+    stage_lds(ds, dY + (uint64_t)r0 * N, rows * N);
+    __syncthreads();
+    const uint32_t n = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float acc[WSLOTS];
+#pragma unroll
+    for (uint32_t j = 0; j < WSLOTS; ++j)
+        acc[j] = 0.f;
+    if (n < N) {
+        const uint32_t b1 = min(rows, 64 * (w + 1));
+#pragma unroll 4
+        for (uint32_t b = 64 * w; b < b1; ++b) {
+            const float d = ds[b * N + n];
+            const float *x = xs + b * XSTRIDE;
+#pragma unroll
+            for (uint32_t j = 0; j < WSLOTS; ++j)
+                acc[j] = fmaf(x[j], d, acc[j]);
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (uint32_t j = 0; j < WSLOTS; ++j)
+            red[w - 1][j][n] = acc[j];
+    }
     __syncthreads();
     if (w == 0 && n < N) {
-        const float s = (part[0][threadIdx.x] + part[1][threadIdx.x]) +
-                        (part[2][threadIdx.x] + part[3][threadIdx.x]);
-        if (k < K)
-            dW[(uint64_t)k * N + n] = s;
-        else
-            dbias[n] = s;
+        float *o = out + (uint64_t)blockIdx.x * (K + 1) * N;
+#pragma unroll
+        for (uint32_t j = 0; j < WSLOTS; ++j) {
+            const uint32_t k = k0 + j;
+            if (k <= K)
+                o[(uint64_t)k * N + n] = ((acc[j] + red[0][j][n]) + red[1][j][n]) + red[2][j][n];
+        }
     }
+}
+
+// Stage two: dW[i] = sum over row blocks r (in order) of part[r][i].
+__global__ void dense_bwd_weight_sum(const float *__restrict__ part, float *__restrict__ dW,
+                                     uint32_t blocks, uint32_t count)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count)
+        return;
+    float s = 0.f;
+    for (uint32_t r = 0; r < blocks; ++r)
+        s += part[(uint64_t)r * count + i];
+    dW[i] = s;
 }
 
 // Masked MSE over B x N: loss = sum M (Y - T)^2 / sum M and
@@ -90,6 +189,7 @@ __global__ __launch_bounds__(1024) void mse_grad(const float *__restrict__ Y,
 {
     __shared__ float s_m[1024], s_e[1024];
     float sm = 0.f, se = 0.f;
+#pragma unroll 8
     for (uint64_t i = threadIdx.x; i < count; i += 1024) {
         const float d = Y[i] - T[i];
         sm += M[i];
@@ -109,6 +209,7 @@ __global__ __launch_bounds__(1024) void mse_grad(const float *__restrict__ Y,
     if (threadIdx.x == 0 && loss)
         *loss = s_e[0] / tot;
     const float scale = 2.f / tot;
+#pragma unroll 8
     for (uint64_t i = threadIdx.x; i < count; i += 1024)
         dY[i] = scale * M[i] * (Y[i] - T[i]);
 }
@@ -170,11 +271,11 @@ mpm_status mpm_mlp_forward(const float *d_theta, const float *d_x, uint32_t batc
         const float *W = d_theta + layer_off(l);
         const float *b = W + (uint64_t)K * N;
         float *out = l < 3 ? d_act + (uint64_t)l * batch * MPM_MLP_HIDDEN : d_y;
-        const uint32_t nb = blocks_for((uint64_t)batch * N, 256);
+        const uint32_t nb = blocks_for((uint64_t)batch * N, 1024);
         if (l < 3)
-            hipLaunchKernelGGL(dense_fwd<true>, dim3(nb), dim3(256), 0, s, in, W, b, out, batch, K, N);
+            hipLaunchKernelGGL(dense_fwd<true>, dim3(nb), dim3(1024), 0, s, in, W, b, out, batch, K, N);
         else
-            hipLaunchKernelGGL(dense_fwd<false>, dim3(nb), dim3(256), 0, s, in, W, b, out, batch, K, N);
+            hipLaunchKernelGGL(dense_fwd<false>, dim3(nb), dim3(1024), 0, s, in, W, b, out, batch, K, N);
         in = out;
     }
     return hip_check("mpm_mlp_forward");
@@ -205,13 +306,23 @@ mpm_status mpm_mlp_backward(const float *d_theta, const float *d_x, const float 
         const float *W = d_theta + layer_off(l);
         const float *A_prev = l == 0 ? d_x : d_act + (uint64_t)(l - 1) * batch * MPM_MLP_HIDDEN;
         float *dW = d_grad + layer_off(l);
-        float *db = dW + (uint64_t)K * N;
-        hipLaunchKernelGGL(dense_bwd_weight, dim3(K + 1, blocks_for(N, 64)), dim3(256), 0, s, A_prev,
-                           g, dW, db, batch, K, N);
+        // the gradient buffer this layer's data gradient will use is free
+        // until then: it holds the partial weight gradients (at most
+        // ceil(batch / 256) x 65 x 64 floats, within batch x 64 when there
+        // is more than one row block)
+        const uint32_t nrb = blocks_for(batch, WROWS);
+        const uint32_t cnt = (K + 1) * N;
+        float *part = nrb > 1 ? buf[l & 1] : dW;
+        const uint32_t quarters = (K + 1 + WSLOTS - 1) / WSLOTS;
+        hipLaunchKernelGGL(dense_bwd_weight, dim3(nrb, quarters), dim3(256), 0, s, A_prev, g, part,
+                           batch, K, N);
+        if (nrb > 1)
+            hipLaunchKernelGGL(dense_bwd_weight_sum, dim3(blocks_for(cnt, 256)), dim3(256), 0, s,
+                               part, dW, nrb, cnt);
         if (l > 0) {
             float *dX = buf[l & 1];
-            hipLaunchKernelGGL(dense_bwd_data, dim3(blocks_for((uint64_t)batch * K, 256)), dim3(256), 0,
-                               s, g, W, A_prev, dX, batch, K, N);
+            hipLaunchKernelGGL(dense_bwd_data, dim3(blocks_for((uint64_t)batch * K, 1024)), dim3(1024),
+                               0, s, g, W, A_prev, dX, batch, K, N);
             g = dX;
         }
     }

@@ -49,16 +49,20 @@ def build_db(tuner: tune.Tuner, sets_idx, stream_dev, reqs, log=None):
     return feats, ms, chunk_factors(ms, chunk, nch)
 
 
-def chunk_factors(ms: np.ndarray, chunk: np.ndarray, nchunks: np.ndarray) -> np.ndarray:
-    """Per variant, the median over a timing database of longest chunk time
-    x chunks / share: a request's longest chunk is about its share times this
-    factor over its number of chunks (the factor is near the launch's
-    workgroup count when a request's chunks cost alike)."""
+def chunk_factors(ms: np.ndarray, chunk: np.ndarray, nchunks: np.ndarray,
+                  quantile: float = 0.9) -> np.ndarray:
+    """Per variant, a high quantile over a timing database of longest chunk
+    time x chunks / share: a request's longest chunk is at most about its
+    share times this factor over its number of chunks (the factor is near
+    the launch's workgroup count when a request's chunks cost alike). The
+    learned policy estimates chunks from predicted costs with it; a high
+    quantile keeps the scheduler from trusting short estimates of chunks
+    that turn out long (the plan then waits for them)."""
     f = np.ones(ms.shape[1])
     for k in range(ms.shape[1]):
         ok = np.isfinite(ms[:, k]) & (ms[:, k] > 0) & np.isfinite(chunk[:, k])
         if ok.any():
-            f[k] = float(np.median(chunk[ok, k] * nchunks[ok, k] / ms[ok, k]))
+            f[k] = float(np.quantile(chunk[ok, k] * nchunks[ok, k] / ms[ok, k], quantile))
     return f
 
 
