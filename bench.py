@@ -649,6 +649,7 @@ def batch_selection(args) -> dict:
         "text_bytes": res["text_bytes"],
         "launches": {k: res[f"{k}_launches"] for k in ("exhaustive", "learned", "default")},
         "pick_agreement": round(res["pick_agreement"], 4),
+        "chunk_safety": round(res["chunk_safety"], 3),
         "time_regret_tuned": {k: round(v, 4) for k, v in res["time_regret_tuned"].items()},
         "selection_overhead_s": {k: round(v, 4) for k, v in res["selection_overhead_s"].items()},
         "train_requests": args.train_requests,

@@ -162,13 +162,19 @@ class Selector:
     needs), `time` predicts each variant's log milliseconds per request (what
     the batch planner's queue order needs)."""
 
-    def __init__(self, rank: _Ensemble, timing: _Ensemble, chunk_factor=None):
+    def __init__(self, rank: _Ensemble, timing: _Ensemble, chunk_factor=None,
+                 chunk_safety: float = 1.0):
         self.rank = rank
         self.timing = timing
         # per variant: a request's longest chunk time ~ its cost x factor /
         # its number of chunks (fitted on the timing database)
         self.chunk_factor = (np.ones(N_OUT) if chunk_factor is None
                              else np.asarray(chunk_factor, np.float64))
+        # predicted costs are multiplied by this before they estimate the
+        # longest chunks a plan waits for: a batch ends with its longest
+        # chunk, the maximum over many requests, which an underestimated
+        # cost would let the scheduler accept
+        self.chunk_safety = float(chunk_safety)
 
     @classmethod
     def fit(cls, feats: np.ndarray, ms: np.ndarray, n_nets: int = 5, steps: int = 2000,
@@ -181,7 +187,13 @@ class Selector:
         rank = _Ensemble.fit(feats, np.where(valid, rel, 0.0), valid, n_nets, steps, lr, seed, device)
         timing = _Ensemble.fit(feats, np.log(safe), valid, max(1, n_nets // 2), steps, lr,
                                seed + 100, device)
-        sel = cls(rank, timing, chunk_factor)
+        # the 99th percentile of measured / predicted cost over the timing
+        # database (clipped to [1, 3]): on requests it was not trained on the
+        # ensemble errs more than on these
+        pred = np.exp(np.clip(timing.predict(feats), -30.0, 30.0))
+        ratio = (safe / pred)[valid]
+        safety = float(np.clip(np.quantile(ratio, 0.99), 1.0, 3.0)) if ratio.size else 1.0
+        sel = cls(rank, timing, chunk_factor, safety)
         sel.history = {"rank": rank.history, "time": timing.history}
         return sel
 
@@ -209,10 +221,12 @@ class Selector:
         d = self.rank.state("rank")
         d.update(self.timing.state("time"))
         d["chunk_factor"] = self.chunk_factor
+        d["chunk_safety"] = np.array([self.chunk_safety])
         np.savez(path, **d)
 
     @classmethod
     def load(cls, path: str, device="cuda"):
         z = np.load(path)
         return cls(_Ensemble.from_state(z, "rank", device), _Ensemble.from_state(z, "time", device),
-                   z["chunk_factor"] if "chunk_factor" in z else None)
+                   z["chunk_factor"] if "chunk_factor" in z else None,
+                   float(z["chunk_safety"][0]) if "chunk_safety" in z else 1.0)

@@ -326,7 +326,7 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
                     for i in range(R)])
     ms_learned = np.where(fallback[:, None], ms, ms_pred)
     chunk_learned = np.where(fallback[:, None], chunk,
-                             ms_pred * selector.chunk_factor[None, :] / nch)
+                             ms_pred * selector.chunk_safety * selector.chunk_factor[None, :] / nch)
     final = schedule(np.where(fallback, exh_req, learned), ms_learned, chunk_learned, valid_r,
                      pset, keys)
     default = np.array([uniform_choice(default_variant, valid_r[i]) for i in range(R)])
@@ -357,6 +357,7 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
     res["regret"] = 1.0 - res["learned_gbps"] / res["exhaustive_gbps"]
     res["gain_over_default"] = res["learned_gbps"] / res["default_gbps"] - 1.0
     res["fallback_rate"] = float(fallback.mean())
+    res["chunk_safety"] = selector.chunk_safety
     res["selection_overhead_s"] = {"features": t_feat, "inference": t_infer,
                                    "fallback_tuning": t_fallback, "exhaustive_tuning": t_exh}
     # how often the learned pick (before fallback) equals the per-request
@@ -379,5 +380,5 @@ def evaluate(b, tuner: tune.Tuner, selector: Selector, default_variant: int,
     res["matches"] = int(np.sum(caps))
     res["_state"] = dict(arena=arena, offs=offs, lens=lens, pset=pset, caps=caps, ms=ms,
                          ms_pred=ms_pred, exh=exh, final=final, default=default,
-                         learned=learned, fallback=fallback)
+                         learned=learned, fallback=fallback, chunk=chunk)
     return res
