@@ -924,6 +924,43 @@ struct AcWalk {
         walk(text, base + lo, end, cb);
     }
 
+    // One lane of dense output (16 starts): its 16 + m - 1 bytes as two or
+    // three 16-byte pieces requested together, then walked from registers,
+    // instead of a piece followed by single-byte loads that each wait out a
+    // round trip. Other ranges (the last lanes of a text, misaligned text,
+    // m > 33) take lane().
+    static constexpr bool LANE16 = true;
+    template <class F>
+    __device__ __forceinline__ void lane16(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
+                                           uint32_t lo, uint32_t hi, F &&cb) const
+    {
+        const uint64_t p = base + lo;
+        const uint32_t np = m <= 17 ? 2u : 3u;  // pieces holding 16 + m - 1 bytes
+        if (hi - lo != 16 || m > 33 || p + 16 * np > n || (((uintptr_t)(text + p)) & 15u)) {
+            lane(text, n, base, lo, hi, cb);
+            return;
+        }
+        glb_cptr<v4u> q = (glb_cptr<v4u>)(text + p);
+        const v4u r0 = q[0], r1 = q[1];
+        const v4u r2 = np == 3 ? q[2] : r1;
+        uint32_t c0[4], c1[4], c2[4];
+        cols16(r0, c0);
+        cols16(r1, c1);
+        cols16(r2, c2);
+        const int steps = 15 + (int)m;
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < 48; ++k) {
+            if (k < steps) {
+                const uint32_t col = k < 16 ? col_of(c0, k) : k < 32 ? col_of(c1, k - 16)
+                                                                     : col_of(c2, k - 32);
+                s = next(s, col);
+                if (s >= first_term)
+                    cb(p + k + 1 - m, s - first_term);
+            }
+        }
+    }
+
     // Two lane ranges of the same chunk walked in lockstep (text 16-byte
     // aligned), or one after the other.
     template <class FA, class FB>
@@ -1349,6 +1386,7 @@ struct WmWalk {
     static constexpr int ILP = 1;
     static constexpr bool DESC = false;
     static constexpr bool STAGE = false;  // reads text through registers
+    static constexpr bool LANE16 = false;  // dense lanes walk with lane()
     static constexpr bool InLds = P == PL_LDS;
     // PL_HOT: SHIFT (read for every window) in LDS, the buckets (read only
     // for windows with a zero shift) in global memory.
@@ -1724,15 +1762,24 @@ __device__ __forceinline__ void process_chunk_dense(const Walk &wk, glb_cptr<uin
     const uint32_t hi = (l0 + DL) < starts ? (l0 + DL) : (uint32_t)starts;
     LDS_AS uint32_t *mk = lds_at<uint32_t>(mark_lds);
 
-    // Phase A: marks and the lane's count of ids.
+    // Phase A: marks and the lane's count of ids. The wave clears its own
+    // 64 * DL marks, 64 consecutive ones per store (bank-conflict free);
+    // its LDS operations complete in program order, so each lane's marks
+    // below land after the clearing.
+    const uint32_t wmk = (threadIdx.x & ~63u) * DL;
 #pragma unroll
     for (uint32_t j = 0; j < DL; ++j)
-        mk[l0 + j] = MARK_NONE;
+        mk[wmk + j * 64 + (threadIdx.x & 63u)] = MARK_NONE;
+    __builtin_amdgcn_wave_barrier();
     uint32_t nid[1] = {0};
-    wk.lane(text, n, base, lo, hi, [&](uint64_t start, uint32_t u) {
+    auto mark = [&](uint64_t start, uint32_t u) {
         mk[(uint32_t)(start - base)] = u;
         nid[0] += im.count(u);
-    });
+    };
+    if constexpr (Walk::LANE16)
+        wk.lane16(text, n, base, lo, hi, mark);
+    else
+        wk.lane(text, n, base, lo, hi, mark);
 
     // Phase B: offsets (its barriers also publish the marks to the wave).
     const bool last = lt + 1 == nt;

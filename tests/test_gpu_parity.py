@@ -185,6 +185,28 @@ def test_dense_output_all_placements(mpm, algo):
         assert_same(got, (want[0][:cap], want[1][:cap]), f"dense prefix {cap}")
 
 
+@pytest.mark.parametrize("m", [1, 5, 16, 17, 18, 33, 34])
+def test_dense_output_pattern_lengths(mpm, m):
+    """Dense Aho-Corasick lanes read their 16 + m - 1 bytes as two (m <= 17)
+    or three (m <= 33) 16-byte pieces up front and walk them from registers;
+    longer patterns, misaligned text and the lanes near the text's end take
+    the byte walk. Every length boundary, at text offsets 0 and 3, for texts
+    ending inside a lane and inside the last pieces."""
+    t = synth.est_text(300_000, seed=60 + m)
+    ps = synth.pattern_set(t, d=300, m=m, n_planted=200, seed=61 + m)
+    ix = mpm.build_ac(ps.patterns, upload=True)
+    for nn in (len(t), 16 * 1024 * 5 + 16 + m, 16 * 1024 * 5 + 47, 16 * 1024 * 2 + 9):
+        tt = t[:nn]
+        want = oracle.Win(ps.patterns).scan(tt)
+        for pl in (0, 2):
+            for mis in (0, 3):
+                v = dict(block_threads=1024, placement=pl, flags=mpm.VARIANT_DENSE)
+                say(f"[dense-m] m={m} n={nn} misalign={mis} {v}")
+                got = gpu_pairs(mpm, ix, tt, mpm.variant(**v), misalign=mis)
+                assert_same(got, want, f"dense m={m} n={nn} mis={mis} {v}")
+        assert len(want[0]) > 0
+
+
 @pytest.mark.parametrize("algo", ["ac", "wm"])
 def test_capacity_overflow_keeps_sorted_prefix(mpm, small, algo):
     text, P, want = small
