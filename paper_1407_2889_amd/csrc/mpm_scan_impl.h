@@ -201,6 +201,28 @@ __device__ __forceinline__ uint64_t look_back(uint64_t *status, uint64_t g, uint
     return excl;
 }
 
+// Exclusive prefix sum of c over the lanes of a wave, and the wave's total,
+// one bit plane at a time: each plane is a ballot whose lanes below this one
+// are counted by mbcnt. As many planes as the largest c has bits (one when
+// every c is 0 or 1), each a few ALU instructions, where a shuffle scan
+// waits out six LDS-crossbar round trips.
+__device__ __forceinline__ uint32_t wave_excl_sum(uint32_t c, uint32_t &total)
+{
+    uint32_t pre = 0, tot = 0;
+#pragma unroll 1
+    for (uint32_t b = 0; b < 32; ++b) {
+        const uint64_t bal = __ballot((c >> b) & 1u);
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        pre += below << b;
+        tot += (uint32_t)__popcll(bal) << b;
+        if (b == 31 || __ballot((c >> (b + 1)) != 0u) == 0)
+            break;
+    }
+    total = tot;
+    return pre;
+}
+
 // Offsets of a chunk's virtual lanes in the text's output. A chunk holds
 // I * W virtual lanes in text order; lane t runs virtual lanes t, t + W, ...
 // cnt[v] is the number of pairs of this lane's v-th virtual lane; ob[v]
@@ -213,23 +235,14 @@ __device__ __forceinline__ void chunk_offsets(const uint32_t (&cnt)[I], uint64_t
 {
     constexpr int NW = W / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x[I];
+    uint32_t x[I], tot[I];  // exclusive prefix within the wave, wave total
 #pragma unroll
     for (int v = 0; v < I; ++v)
-        x[v] = cnt[v];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-        for (int v = 0; v < I; ++v) {
-            const uint32_t y = __shfl_up(x[v], o, 64);
-            if (lane >= o)
-                x[v] += y;
-        }
-    }
-    if (lane == 63) {
+        x[v] = wave_excl_sum(cnt[v], tot[v]);
+    if (lane == 0) {
 #pragma unroll
         for (int v = 0; v < I; ++v)
-            s_scan[v * NW + wave] = x[v];
+            s_scan[v * NW + wave] = tot[v];
     }
     __syncthreads();
     if (wave == 0) {
@@ -252,7 +265,7 @@ __device__ __forceinline__ void chunk_offsets(const uint32_t (&cnt)[I], uint64_t
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < I; ++v)
-        ob[v] = s_scan[I * NW] + s_scan[v * NW + wave] + (x[v] - cnt[v]);
+        ob[v] = s_scan[I * NW] + s_scan[v * NW + wave] + x[v];
 }
 
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
@@ -928,7 +941,9 @@ struct AcWalk {
     // three 16-byte pieces requested together, then walked from registers,
     // instead of a piece followed by single-byte loads that each wait out a
     // round trip. Other ranges (the last lanes of a text, misaligned text,
-    // m > 33) take lane().
+    // m > 33) take the piece-or-byte walk, which (unlike the line walk of
+    // long ranges) keeps few registers live: the dense kernel then fits its
+    // registers without spilling.
     static constexpr bool LANE16 = true;
     template <class F>
     __device__ __forceinline__ void lane16(glb_cptr<uint8_t> text, uint64_t n, uint64_t base,
@@ -937,7 +952,13 @@ struct AcWalk {
         const uint64_t p = base + lo;
         const uint32_t np = m <= 17 ? 2u : 3u;  // pieces holding 16 + m - 1 bytes
         if (hi - lo != 16 || m > 33 || p + 16 * np > n || (((uintptr_t)(text + p)) & 15u)) {
-            lane(text, n, base, lo, hi, cb);
+            if (lo >= hi)
+                return;
+            uint64_t end = base + hi + m - 1;
+            if (end > n)
+                end = n;
+            uint32_t s = 0;
+            walk_rest(s, text, p, end, cb);
             return;
         }
         glb_cptr<v4u> q = (glb_cptr<v4u>)(text + p);
@@ -1800,15 +1821,9 @@ __device__ __forceinline__ void process_chunk_dense(const Walk &wk, glb_cptr<uin
         if (u != MARK_NONE)
             im.span(u, b, e);
         const uint32_t c = e - b;
-        uint32_t x = c;
-#pragma unroll
-        for (int s = 1; s < 64; s <<= 1) {
-            const uint32_t y = __shfl_up(x, s, 64);
-            if (lane >= s)
-                x += y;
-        }
-        const uint32_t round = __shfl(x, 63, 64);
-        uint64_t q = o + (x - c);
+        uint32_t round;
+        const uint32_t pre = wave_excl_sum(c, round);
+        uint64_t q = o + pre;
         const uint32_t pos = (uint32_t)(base + p);
         for (uint32_t j = b; j < e && q < cap; ++j, ++q)
             out[q] = v2u{pos, im.id(j)};
@@ -1885,11 +1900,22 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     if (threadIdx.x == 0)
         s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
+    // Dense output (many short chunks): thread 0 takes the next chunk's
+    // ticket as soon as it starts a chunk, so the atomic's round trip
+    // overlaps the chunk's work. A workgroup holds at most one chunk ahead of
+    // the one it runs, which waits only on earlier chunks: the earliest
+    // unfinished chunk is always running. The other kernels run few, long
+    // chunks and keep the register for the walk.
+    uint64_t next_t = 0;
+    if (Dense && threadIdx.x == 0)
+        next_t = take_ticket(hdr);
     while (true) {
         if (threadIdx.x == 0) {
-            const uint64_t t = take_ticket(hdr);
+            const uint64_t t = Dense ? next_t : take_ticket(hdr);
             s_tile = t;
             if (t < ntiles) {
+                if (Dense)
+                    next_t = take_ticket(hdr);
                 if (ntexts == 1) {
                     s_td = sd.single;
                 } else {  // the text whose chunk range holds t
