@@ -1900,22 +1900,11 @@ __global__ __launch_bounds__(W) void scan_kernel(typename Walk::Dev a, ScanDev s
     if (threadIdx.x == 0)
         s_epoch = __hip_atomic_load(&hdr[WS_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
-    // Dense output (many short chunks): thread 0 takes the next chunk's
-    // ticket as soon as it starts a chunk, so the atomic's round trip
-    // overlaps the chunk's work. A workgroup holds at most one chunk ahead of
-    // the one it runs, which waits only on earlier chunks: the earliest
-    // unfinished chunk is always running. The other kernels run few, long
-    // chunks and keep the register for the walk.
-    uint64_t next_t = 0;
-    if (Dense && threadIdx.x == 0)
-        next_t = take_ticket(hdr);
     while (true) {
         if (threadIdx.x == 0) {
-            const uint64_t t = Dense ? next_t : take_ticket(hdr);
+            const uint64_t t = take_ticket(hdr);
             s_tile = t;
             if (t < ntiles) {
-                if (Dense)
-                    next_t = take_ticket(hdr);
                 if (ntexts == 1) {
                     s_td = sd.single;
                 } else {  // the text whose chunk range holds t
